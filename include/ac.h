@@ -1,0 +1,216 @@
+/*
+ * ac.h -- Aho-Corasick multi-pattern matching on MI355X (gfx950): C ABI.
+ *
+ * The paper (section III.A) splits Aho-Corasick into two stages: building a
+ * string-matching machine from the keywords, then reading the input string
+ * once with that machine.  Section IV.B describes the library interface the
+ * authors used: an array of pattern strings and one input string in, the
+ * matched pattern and its position in the input out.  This header exposes
+ * the same two stages:
+ *
+ *   ac_build      stage 1, on the host: keyword trie (goto function),
+ *                 breadth-first failure links and output sets, compiled into
+ *                 a dense transition table (goto completed through failure
+ *                 links) plus output-set offsets, then copied to the GPU.
+ *   ac_scan       stage 2, on the GPU: every (pattern id, end position)
+ *                 occurrence in a device-resident text, written in
+ *                 (end position, pattern id) order.
+ *   ac_scan_batch many independent (text, dictionary) instances in one
+ *                 sequence of persistent launches.
+ *   ac_encode     letters -> symbol codes, or DNA -> 2 bits per base.
+ *
+ * Conventions:
+ *   - Symbols are codes 0 .. sigma-1.  Pattern i (0-based, input order) is
+ *     symbols[offsets[i] .. offsets[i+1]); patterns may repeat and each copy
+ *     is reported under its own id.
+ *   - A match is (pattern_id, end_pos) with end_pos the 0-based index of the
+ *     pattern's last symbol in the text.
+ *   - Text formats: AC_TEXT_U8 holds one code per byte; AC_TEXT_2BIT (sigma
+ *     must be 4) holds four codes per byte, base i in byte i/4 at bits
+ *     2*(i%4) and 2*(i%4)+1 (least significant first).
+ *   - Device pointers are plain HIP device addresses (hipMalloc or a torch
+ *     tensor's data pointer); host pointers are ordinary memory.  A stream
+ *     argument is a hipStream_t passed as void* (NULL = the null stream).
+ *   - Every function returns AC_OK (0) or a negative AC_E_* code and never
+ *     throws.  Arguments are validated on the host before anything is
+ *     enqueued; on an error nothing is enqueued.  Launch errors map to
+ *     AC_E_HIP.
+ *   - Thread safety: a dictionary is read-only after ac_build; scans with
+ *     the same dictionary may run concurrently on different streams.
+ */
+#ifndef AC_H
+#define AC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AC_OK 0
+#define AC_E_INVALID (-1)        /* null pointer, bad enum value or size     */
+#define AC_E_EMPTY_PATTERN (-2)  /* a pattern of length 0                    */
+#define AC_E_SYMBOL (-3)         /* a pattern symbol >= sigma                */
+#define AC_E_TOO_LARGE (-4)      /* text >= 2^32 symbols, table >= 2^32 B    */
+#define AC_E_NOMEM (-5)          /* host or device allocation failed         */
+#define AC_E_OVERFLOW (-6)       /* workspace smaller than required          */
+#define AC_E_HIP (-7)            /* a HIP runtime call or launch failed      */
+#define AC_E_NO_DEVICE (-8)      /* dictionary was built without GPU tables  */
+
+#define AC_TEXT_U8 0
+#define AC_TEXT_2BIT 1
+
+#define AC_ALPHA_DNA 0      /* A C G T -> 0 1 2 3 (either case)           */
+#define AC_ALPHA_PROTEIN 1  /* A C D E F G H I K L M N P Q R S T V W Y -> 0..19 */
+
+#define AC_PLACE_AUTO 0     /* library chooses                              */
+#define AC_PLACE_LDS 1      /* whole table in LDS (must fit)                */
+#define AC_PLACE_GLOBAL 2   /* table read through L1/L2 from HBM            */
+#define AC_PLACE_HYBRID 3   /* first hot_states rows in LDS, rest global    */
+
+#define AC_BUILD_HOST_ONLY 1u /* compile tables on the host only (no GPU)   */
+
+typedef struct ac_dict ac_dict;
+typedef struct ac_batch ac_batch;
+
+/* One occurrence: 8 bytes. */
+typedef struct {
+    uint32_t pattern_id;
+    uint32_t end_pos;
+} ac_match;
+
+typedef struct {
+    uint32_t sigma;      /* alphabet size, 2..256                            */
+    uint32_t placement;  /* AC_PLACE_* default for scans with this dict      */
+    uint32_t flags;      /* AC_BUILD_HOST_ONLY or 0                          */
+    uint32_t hot_states; /* rows kept in LDS by AC_PLACE_HYBRID; 0 = fill LDS */
+} ac_build_opts;
+
+typedef struct {
+    uint32_t states;             /* automaton states (root = 0)            */
+    uint32_t patterns;
+    uint32_t sigma;
+    uint32_t min_len, max_len;   /* shortest / longest pattern             */
+    uint32_t first_output_state; /* states >= this have a non-empty output */
+    uint32_t max_output;         /* largest output set                     */
+    uint32_t placement;          /* default placement chosen by ac_build   */
+    uint32_t hot_states;         /* rows in LDS for AC_PLACE_HYBRID        */
+    uint32_t has_device;         /* 1 if the GPU tables exist              */
+    uint64_t output_entries;     /* sum of output-set sizes                */
+    uint64_t table_bytes;        /* dense table, bytes                     */
+    double build_ms;             /* host time of ac_build, tables only     */
+} ac_dict_info;
+
+/* Launch shape of a scan.  Zero fields take the library's choice. */
+typedef struct {
+    uint32_t chunk;         /* text symbols owned by one lane, multiple of 64 */
+    uint32_t block_threads; /* 64..1024, multiple of 64                      */
+    uint32_t placement;     /* AC_PLACE_*; AUTO = the dictionary's default   */
+    uint32_t blocks_per_cu; /* persistent blocks per compute unit            */
+} ac_tune;
+
+/* ---------------------------------------------------------------- stage 1
+ * ac_build: compile patterns into a dictionary (section III.A, Figure 1:
+ * goto function, failure function, output function).
+ *   symbols, offsets  host CSR list of n_patterns >= 1 patterns; offsets has
+ *                     n_patterns + 1 entries, offsets[0] = 0.  Copied; the
+ *                     caller may free them on return.
+ *   opts              may be NULL only for sigma = 4 defaults.
+ *   out               receives the dictionary; release with ac_destroy.
+ * Errors: AC_E_INVALID, AC_E_EMPTY_PATTERN, AC_E_SYMBOL, AC_E_TOO_LARGE
+ * (more than 2^27 states or a table of 2^32 bytes or more), AC_E_NOMEM,
+ * AC_E_HIP (device upload failed). */
+int ac_build(const uint8_t *symbols, const uint64_t *offsets, uint32_t n_patterns,
+             const ac_build_opts *opts, ac_dict **out);
+
+/* Release a dictionary (host and device memory).  NULL is ignored.  The
+ * caller must have synchronised every stream that uses it. */
+void ac_destroy(ac_dict *dict);
+
+int ac_dict_get_info(const ac_dict *dict, ac_dict_info *info);
+
+/* Host copies of the compiled tables, for inspection and CPU checks:
+ *   delta    states*sigma entries: delta[s*sigma + a] = next state of s on
+ *            symbol a (renumbered ids; root = 0).
+ *   out_off  (states - first_output_state + 1) offsets into out_ids for the
+ *            output set of state first_output_state + k.
+ *   out_ids  output_entries pattern ids, each set sorted ascending.
+ *   depth    states entries: length of the prefix spelled by each state.
+ * Any pointer may be NULL to skip that table. */
+int ac_debug_export(const ac_dict *dict, uint32_t *delta, uint32_t *out_off,
+                    uint32_t *out_ids, uint32_t *depth);
+
+/* ---------------------------------------------------------------- encoding
+ * ac_encode: d_ascii (n letters, device) -> d_out (device) as AC_TEXT_U8
+ * codes (n bytes) or, for AC_ALPHA_DNA only, AC_TEXT_2BIT ((n+3)/4 bytes,
+ * unused bits of the last byte zero).  Letters outside the alphabet are
+ * encoded as code 0 and counted into *d_invalid (device uint64, may be NULL;
+ * it is overwritten, not accumulated).  Stream-ordered. */
+int ac_encode(const uint8_t *d_ascii, uint64_t n, uint32_t alphabet, uint32_t fmt,
+              void *d_out, uint64_t *d_invalid, void *stream);
+
+/* ---------------------------------------------------------------- stage 2
+ * ac_scan: all occurrences of the dictionary's patterns in a device text
+ * (section III.A, stage 2: one pass over the input).
+ *   d_text      device text of n symbols in format fmt (n < 2^32).  Codes
+ *               >= sigma give unspecified matches but never an access
+ *               outside the dictionary's tables.
+ *   d_out       device array of capacity ac_match slots.  The first
+ *               min(total, capacity) matches in (end_pos, pattern_id) order
+ *               are written; slots beyond are untouched.
+ *   d_count     device uint64: receives the total number of matches, which
+ *               may exceed capacity (then re-run with a larger d_out).
+ *   tune        NULL = library choice.
+ *   d_workspace device scratch of workspace_bytes (see
+ *               ac_scan_workspace_size), or NULL to let the library take it
+ *               from HIP's stream-ordered allocator for this call.
+ *   stream      hipStream_t as void*.
+ * Returns after enqueueing; results are valid once the stream reaches this
+ * point.  Concurrent calls must not share a workspace. */
+int ac_scan_workspace_size(const ac_dict *dict, uint64_t n, uint32_t fmt,
+                           const ac_tune *tune, uint64_t *bytes);
+int ac_scan(const ac_dict *dict, const void *d_text, uint64_t n, uint32_t fmt,
+            ac_match *d_out, uint64_t capacity, uint64_t *d_count,
+            const ac_tune *tune, void *d_workspace, uint64_t workspace_bytes,
+            void *stream);
+
+/* ---------------------------------------------------------------- batches
+ * One instance of a batch: its own dictionary, text, output and count,
+ * with the meaning of the same-named ac_scan arguments. */
+typedef struct {
+    const ac_dict *dict;
+    const void *d_text;
+    uint64_t n;
+    uint32_t fmt;
+    uint32_t reserved;
+    ac_match *d_out;
+    uint64_t capacity;
+    uint64_t *d_count;
+} ac_batch_item;
+
+/* ac_batch_create: plan a batch once (work list of (instance, chunk range)
+ * tiles grouped by instance, descriptors uploaded to the device, workspace
+ * allocated) so that ac_batch_run only launches kernels: it can be replayed
+ * and captured in a hipGraph.  The items' buffers must stay valid for the
+ * life of the plan. */
+int ac_batch_create(const ac_batch_item *items, uint32_t n_items, const ac_tune *tune,
+                    ac_batch **out);
+int ac_batch_run(ac_batch *batch, void *stream);
+void ac_batch_destroy(ac_batch *batch);
+
+/* ac_scan_batch: plan + run + release in one call (the plan's memory is
+ * released after the stream reaches the end of the batch). */
+int ac_scan_batch(const ac_batch_item *items, uint32_t n_items, const ac_tune *tune,
+                  void *stream);
+
+/* ---------------------------------------------------------------- misc */
+const char *ac_status_str(int status);
+
+/* Device properties the launch heuristics use (compute units, LDS bytes per
+ * block).  Returns AC_E_HIP when no GPU is visible. */
+int ac_device_info(uint32_t *compute_units, uint32_t *lds_bytes_per_block);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AC_H */

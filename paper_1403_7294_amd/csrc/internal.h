@@ -1,0 +1,70 @@
+// Internal declarations shared by the host automaton compiler
+// (automaton.cpp), the C-ABI entry points (api.cpp) and the GPU code
+// (scan.hip).  Not part of the public ABI.
+#pragma once
+
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/ac.h"
+
+namespace acx {
+
+// Host form of a compiled dictionary.
+//
+// States are renumbered so that the root is 0, states whose output set is
+// empty come first in breadth-first order (shallow, frequently visited rows
+// first, which is what the LDS-resident "hot" prefix of the table wants), and
+// states with a non-empty output set come last: "state >= first_output" is
+// then the whole match test of the scan.
+struct HostTables {
+    uint32_t sigma = 0;
+    uint32_t states = 0;
+    uint32_t patterns = 0;
+    uint32_t min_len = 0, max_len = 0;
+    uint32_t first_output = 0;
+    uint32_t max_output = 0;
+    std::vector<uint32_t> delta;    // states*sigma, next-state ids
+    std::vector<uint32_t> out_off;  // states-first_output+1
+    std::vector<uint32_t> out_ids;  // concatenated output sets, ids ascending
+    std::vector<uint32_t> depth;    // prefix length spelled by each state
+};
+
+// Stage 1 of the method on the host: trie, failure links, completed
+// transitions, output sets, renumbering.  Returns an AC_* status.
+int compile_automaton(const uint8_t *symbols, const uint64_t *offsets, uint32_t n_patterns,
+                      uint32_t sigma, HostTables *out);
+
+// Exact division of a row byte offset (state * sigma * 4) by sigma * 4:
+// state = (offset >> tz) * inv (mod 2^32), with sigma*4 = 2^tz * odd and
+// inv the inverse of odd modulo 2^32.
+struct RowDiv {
+    uint32_t tz = 0;
+    uint32_t inv = 1;
+};
+RowDiv make_row_div(uint32_t sigma);
+
+}  // namespace acx
+
+// The opaque dictionary handle.
+struct ac_dict {
+    acx::HostTables host;
+    uint32_t placement = AC_PLACE_AUTO;  // default for scans
+    uint32_t hot_states = 0;             // LDS rows for hybrid placement
+    double build_ms = 0.0;
+    // device copies (null when built host-only)
+    int device = -1;
+    uint32_t *d_delta = nullptr;    // states*sigma row byte offsets
+    uint32_t *d_out_off = nullptr;
+    uint32_t *d_out_ids = nullptr;
+    uint64_t table_bytes = 0;
+};
+
+namespace acx {
+// Device-side upload / release (scan.hip).
+int upload_dict(ac_dict *d);
+void release_dict(ac_dict *d);
+// Largest dynamic LDS allocation one block may use, and compute units.
+int device_limits(uint32_t *cus, uint32_t *lds_bytes);
+}  // namespace acx
