@@ -70,6 +70,12 @@ extern "C" {
 
 #define AC_BUILD_HOST_ONLY 1u /* compile tables on the host only (no GPU)   */
 
+/* Work units of the scan: a segment is AC_SEGMENT text symbols; segments
+ * with at least AC_DENSE_SEGMENT_MATCHES matches are written by a whole
+ * wavefront each (the AC_K_EMIT_DENSE kernel), the others by one lane. */
+#define AC_SEGMENT 64
+#define AC_DENSE_SEGMENT_MATCHES 256
+
 typedef struct ac_dict ac_dict;
 typedef struct ac_batch ac_batch;
 
@@ -202,6 +208,24 @@ void ac_batch_destroy(ac_batch *batch);
  * released after the stream reaches the end of the batch). */
 int ac_scan_batch(const ac_batch_item *items, uint32_t n_items, const ac_tune *tune,
                   void *stream);
+
+/* ---------------------------------------------------------------- timing
+ * Kernel timing for measurement.  While enabled, every call above records a
+ * pair of hipEvents on its stream around each kernel it launches (do not
+ * enable it while a stream is being captured into a graph).  ac_timing_read
+ * waits for the recorded events, adds their elapsed times to per-kind totals
+ * and returns them: ms[k] and launches[k] for k < AC_K_KINDS (arrays of
+ * AC_K_KINDS entries, either may be NULL); reset != 0 clears the totals. */
+#define AC_K_ENCODE 0   /* ac_encode                                   */
+#define AC_K_COUNT 1    /* pass 1: walk chunks, count matches per segment */
+#define AC_K_OFFSETS 2  /* prefix sums over tiles                         */
+#define AC_K_SCATTER 3  /* work list of segments with matches             */
+#define AC_K_EMIT 4     /* pass 2, sparse segments: one lane each          */
+#define AC_K_TOTALS 5   /* per-instance totals (batches)                 */
+#define AC_K_EMIT_DENSE 6 /* pass 2, dense segments: one wave each       */
+#define AC_K_KINDS 7
+int ac_timing_enable(int on);
+int ac_timing_read(double *ms, uint64_t *launches, int reset);
 
 /* ---------------------------------------------------------------- misc */
 const char *ac_status_str(int status);

@@ -41,13 +41,20 @@ AC_ALPHA_DNA = 0
 AC_ALPHA_PROTEIN = 1
 AC_PLACE_AUTO, AC_PLACE_LDS, AC_PLACE_GLOBAL, AC_PLACE_HYBRID = 0, 1, 2, 3
 AC_BUILD_HOST_ONLY = 1
+AC_SEGMENT = 64
+AC_DENSE_SEGMENT_MATCHES = 256
 
 # every symbol include/ac.h declares
 ABI_SYMBOLS = [
     "ac_build", "ac_destroy", "ac_dict_get_info", "ac_debug_export", "ac_encode",
     "ac_scan_workspace_size", "ac_scan", "ac_batch_create", "ac_batch_run",
     "ac_batch_destroy", "ac_scan_batch", "ac_status_str", "ac_device_info",
+    "ac_timing_enable", "ac_timing_read",
 ]
+AC_K_ENCODE, AC_K_COUNT, AC_K_OFFSETS, AC_K_SCATTER, AC_K_EMIT, AC_K_TOTALS, AC_K_EMIT_DENSE = \
+    range(7)
+AC_K_KINDS = 7
+KERNEL_NAMES = ["encode", "count", "offsets", "scatter", "emit", "totals", "emit_dense"]
 
 
 class LibraryMissing(RuntimeError):
@@ -133,6 +140,10 @@ def lib():
     L.ac_status_str.restype = ctypes.c_char_p
     L.ac_device_info.argtypes = [ctypes.POINTER(u32), ctypes.POINTER(u32)]
     L.ac_device_info.restype = i
+    L.ac_timing_enable.argtypes = [i]
+    L.ac_timing_enable.restype = i
+    L.ac_timing_read.argtypes = [P, P, i]
+    L.ac_timing_read.restype = i
     _lib = L
     return L
 
@@ -289,6 +300,18 @@ def ac_device_info() -> Tuple[int, int]:
     cu, lds = ctypes.c_uint32(), ctypes.c_uint32()
     _check(lib().ac_device_info(ctypes.byref(cu), ctypes.byref(lds)), "ac_device_info")
     return cu.value, lds.value
+
+
+def ac_timing_enable(on: bool) -> None:
+    _check(lib().ac_timing_enable(1 if on else 0), "ac_timing_enable")
+
+
+def ac_timing_read(reset: bool = False):
+    """{kernel name: (total ms, launches)} since the last reset."""
+    ms = (ctypes.c_double * AC_K_KINDS)()
+    n = (ctypes.c_uint64 * AC_K_KINDS)()
+    _check(lib().ac_timing_read(ms, n, 1 if reset else 0), "ac_timing_read")
+    return {KERNEL_NAMES[k]: (ms[k], n[k]) for k in range(AC_K_KINDS)}
 
 
 # ------------------------------------------------------------------ handles

@@ -24,7 +24,7 @@ ARCH = "gfx950"
 
 HOST_SOURCES = ["automaton.cpp", "api.cpp"]
 HIP_SOURCES = ["scan.hip"]
-DEPS = ["internal.h", "batch.inc"]
+DEPS = ["internal.h", "batch.inc", "device_common.h"]
 
 # packed fp32 instructions are disabled on every HIP compile (they are never
 # needed here and are kept out of the code objects on purpose)

@@ -3,25 +3,31 @@
 //
 // Decomposition (the paper's section IV.A, first design, made exact): lane j
 // owns the end positions [j*C, (j+1)*C) of the text.  It starts at the root
-// max_len-1 (rounded up to a whole 32-bit text word) symbols before j*C, so
-// that by the time it reaches j*C its state is the same one a single pass
-// from the start of the text would hold: the state after reading a text
-// prefix is its longest suffix that is a trie prefix, and no trie prefix is
-// longer than max_len.  Every match is then reported by exactly one lane.
+// max_len-1 symbols (rounded up to a whole 32-bit text word) before j*C, so
+// that from j*C on its state equals the state a single pass from the start
+// of the text would hold: after any text prefix the machine is in the
+// longest suffix of that prefix that is a trie prefix, and no trie prefix is
+// longer than max_len.  Every match is therefore reported by exactly one lane.
 //
-// One scan is four launches on the caller's stream:
-//   k_count     every lane walks its chunk once with one table lookup per
-//               symbol and counts the matches ending in it (sum of output-
-//               set sizes of the states it passes through);
-//   k_tile_scan one block turns per-tile sums into exclusive offsets;
-//   k_scatter   per-chunk output offsets, and the list of chunks that have
-//               at least one match;
-//   k_emit      only the listed chunks are walked again; matches are written
-//               at their final offsets, so the output comes out in
-//               (end position, pattern id) order with no sort, and a
-//               too-small output buffer still receives the first matches.
-// The dense transition table lives in LDS when it fits, in HBM behind the
-// L1/L2 caches otherwise, or split (hot first rows in LDS).
+// A scan is four launches on the caller's stream:
+//   k_count     every lane walks its chunk once, one table lookup per symbol,
+//               and counts the matches ending in each 64-symbol segment (sum
+//               of the output-set sizes of the states entered).  For each
+//               segment with matches it stores the state on entry and the
+//               count; per chunk it stores the total and a segment bit mask.
+//   k_tile_scan one block: exclusive offsets of the per-tile totals.
+//   k_scatter   the work list: every segment with matches, with its entry
+//               state and its first output slot, in text order; segments with
+//               many matches are listed after the others so that lanes of a
+//               wave carry similar amounts of output.
+//   k_emit      one lane per listed segment walks its 64 symbols again from
+//               the stored state and writes each match at its final slot.
+// Matches therefore come out in (end position, pattern id) order with no
+// sort, and a too-small output buffer still receives the first matches.
+//
+// The transition table holds row byte offsets (state * sigma * 4); it lives
+// in LDS when it fits, in HBM behind the L1/L2 caches otherwise, or split
+// with the first (most visited, shallowest) rows in LDS.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -31,18 +37,15 @@
 #include <new>
 #include <vector>
 
+#include "device_common.h"
 #include "internal.h"
 
 namespace acx {
 
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-typedef __amdgpu_buffer_rsrc_t rsrc_t;
-typedef __attribute__((address_space(3))) uint32_t lds_u32;
-typedef __attribute__((address_space(3))) uint8_t lds_u8;
-
-enum { PL_LDS = 1, PL_GLOBAL = 2, PL_HYBRID = 3 };
-
-constexpr uint32_t kLdsPad = 1024;     // zero rows past an LDS table (u8 codes >= sigma)
+constexpr uint32_t kSeg = AC_SEGMENT;     // symbols per segment
+constexpr uint32_t kMaxChunk = 2048;      // 32 segments: one bit each in a chunk mask
+constexpr uint32_t kDenseMatches = AC_DENSE_SEGMENT_MATCHES;  // listed last, one wave each
+constexpr uint32_t kLdsPad = 1024;        // zero bytes after an LDS table (u8 codes >= sigma)
 constexpr uint32_t kEmitThreads = 256;
 constexpr uint32_t kMaxCountThreads = 1024;
 
@@ -77,238 +80,76 @@ struct TileDesc {
     uint32_t pad;
 };
 
-// ------------------------------------------------------------------ helpers
-
-__device__ __forceinline__ rsrc_t make_rsrc(const void *p, uint32_t bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes,
-                                             0x00020000);
-}
-
-__device__ __forceinline__ uint32_t lds_load(uint32_t byte_addr) {
-    extern __shared__ uint32_t dyn_smem[];
-    return *(lds_u32 *)((lds_u8 *)(lds_u32 *)dyn_smem + byte_addr);
-}
-
-template <typename T>
-__device__ __forceinline__ T uniform(T v) {
-    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "");
-    if constexpr (sizeof(T) == 4) {
-        return __builtin_bit_cast(T, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
-    } else {
-        uint64_t x = __builtin_bit_cast(uint64_t, v);
-        uint32_t lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)x);
-        uint32_t hi = __builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
-        return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
-    }
-}
-
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-template <typename T>
-__device__ __forceinline__ T wave_incl_scan(T v) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        T t = __shfl_up(v, o, 64);
-        if (lane >= o) v += t;
-    }
-    return v;
-}
-
-// Block-wide exclusive scan of (a, b); returns totals through ta, tb.
-// Every thread of the block must call it.  Uses 2*16 words of scratch.
-__device__ __forceinline__ void block_excl_scan2(unsigned long long a, uint32_t b,
-                                                 unsigned long long *ea, uint32_t *eb,
-                                                 unsigned long long *ta, uint32_t *tb) {
-    __shared__ unsigned long long s_a[16];
-    __shared__ uint32_t s_b[16];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int nw = (blockDim.x + 63) >> 6;
-    unsigned long long ia = wave_incl_scan(a);
-    uint32_t ib = wave_incl_scan(b);
-    if (lane == 63) {
-        s_a[wid] = ia;
-        s_b[wid] = ib;
-    }
-    __syncthreads();
-    unsigned long long pa = 0, sa = 0;
-    uint32_t pb = 0, sb = 0;
-    for (int w = 0; w < nw; ++w) {
-        if (w == wid) {
-            pa = sa;
-            pb = sb;
-        }
-        sa += s_a[w];
-        sb += s_b[w];
-    }
-    *ea = pa + ia - a;
-    *eb = pb + ib - b;
-    *ta = sa;
-    *tb = sb;
-    __syncthreads();
-}
-
-// Row byte offset -> state number (exact division by sigma*4).
-__device__ __forceinline__ uint32_t row_state(uint32_t e, uint32_t tz, uint32_t inv) {
-    return (e >> tz) * inv;
-}
-
-// One symbol: bits of the text word at compile-time (k) or run-time slot.
-template <int FMT>
-__device__ __forceinline__ uint32_t sym_bytes(uint32_t x, uint32_t k) {
-    // symbol code * 4 (= its byte offset within a table row)
-    if constexpr (FMT == AC_TEXT_2BIT)
-        return __builtin_amdgcn_ubfe(x, 2 * k, 2) << 2;
-    else
-        return __builtin_amdgcn_ubfe(x, 8 * k, 8) << 2;
-}
-
-// Table lookups of a uniform (wave-invariant) table.
-template <int PLACE>
-struct UTable {
-    rsrc_t g;
-    uint32_t hot;
-    __device__ __forceinline__ uint32_t operator()(uint32_t a) const {
-        if constexpr (PLACE == PL_LDS) {
-            return lds_load(a);
-        } else if constexpr (PLACE == PL_GLOBAL) {
-            return __builtin_amdgcn_raw_buffer_load_b32(g, a, 0, 0);
-        } else {
-            uint32_t v;
-            if (a < hot)
-                v = lds_load(a);
-            else
-                v = __builtin_amdgcn_raw_buffer_load_b32(g, a, 0, 0);
-            return v;
-        }
-    }
-};
-
-// Text reads of a uniform text (bounds from the buffer resource: reads past
-// the end return 0).
-struct UText {
-    rsrc_t r;
-    uint32_t bytes4;
-    __device__ __forceinline__ uint32_t word(int w) const {
-        return w < 0 ? 0u : __builtin_amdgcn_raw_buffer_load_b32(r, (uint32_t)w * 4u, 0, 0);
-    }
-    __device__ __forceinline__ u32x4 vec(uint32_t w) const {
-        const uint32_t o = w * 4u;
-        if (o + 16u <= bytes4) return __builtin_amdgcn_raw_buffer_load_b128(r, o, 0, 0);
-        u32x4 v;
-        v.x = __builtin_amdgcn_raw_buffer_load_b32(r, o, 0, 0);
-        v.y = __builtin_amdgcn_raw_buffer_load_b32(r, o + 4, 0, 0);
-        v.z = __builtin_amdgcn_raw_buffer_load_b32(r, o + 8, 0, 0);
-        v.w = __builtin_amdgcn_raw_buffer_load_b32(r, o + 12, 0, 0);
-        return v;
-    }
-};
-
-// Per-lane table and text (batched emission: lanes of a wave may work on
-// different instances).
-struct LTable {
-    const uint32_t *t;
-    uint32_t bytes;
-    __device__ __forceinline__ uint32_t operator()(uint32_t a) const {
-        return a < bytes ? t[a >> 2] : 0u;
-    }
-};
-struct LText {
-    const uint32_t *t;
-    uint32_t bytes4;
-    __device__ __forceinline__ uint32_t word(int w) const {
-        return (w < 0 || (uint32_t)w * 4u >= bytes4) ? 0u : t[w];
-    }
-};
-
-template <int FMT>
-struct Fmt {
-    static constexpr uint32_t SPW = FMT == AC_TEXT_2BIT ? 16 : 4;  // symbols per 32-bit word
-};
-
-// Warm-up: walk warm words ending just before word w0 (words before the text
-// start are skipped, which leaves the state at the root as it must be).
-template <int FMT, class Tab, class Txt>
-__device__ __forceinline__ uint32_t warm_up(const Tab &tab, const Txt &txt, int w0, uint32_t warm) {
-    constexpr uint32_t SPW = Fmt<FMT>::SPW;
-    uint32_t s = 0;
-    for (uint32_t i = 0; i < warm; ++i) {
-        const int w = w0 - (int)warm + (int)i;
-        const uint32_t x = txt.word(w);
-        const bool live = w >= 0;
-#pragma unroll
-        for (uint32_t k = 0; k < SPW; ++k) {
-            const uint32_t ns = tab(s + sym_bytes<FMT>(x, k));
-            s = live ? ns : s;
-        }
-    }
-    return s;
-}
-
 // ------------------------------------------------------------------ count
 
-// Walk chunk j and count the matches that end in it.
+struct ChunkOut {
+    uint32_t m;      // matches ending in the chunk
+    uint32_t mask;   // segments with matches
+    uint32_t dense;  // of which with >= kDenseMatches matches
+};
+
 template <int FMT, int PLACE>
-__device__ __forceinline__ uint32_t walk_count(const UTable<PLACE> &tab, const UText &txt,
-                                               const uint32_t *__restrict__ out_off,
-                                               uint32_t fo, uint32_t fo_state, uint32_t tz,
-                                               uint32_t inv, uint32_t j, uint32_t chunk,
-                                               uint32_t warm, uint32_t lim) {
+__device__ __forceinline__ ChunkOut walk_count(const UTable<PLACE> &tab, const UText &txt,
+                                               const uint32_t *__restrict__ out_off, uint32_t fo,
+                                               uint32_t fo_state, uint32_t tz, uint32_t inv,
+                                               uint32_t j, uint32_t chunk, uint32_t warm,
+                                               uint32_t lim, uint32_t *__restrict__ seg_state,
+                                               uint32_t *__restrict__ seg_m, uint32_t seg0) {
     constexpr uint32_t SPW = Fmt<FMT>::SPW;
-    const uint32_t wpc = chunk / SPW;
+    constexpr uint32_t WPS = kSeg / SPW;  // text words per segment
+    const uint32_t wpc = chunk / SPW, spc = chunk / kSeg;
     const uint32_t w0 = j * wpc;
     uint32_t s = warm_up<FMT>(tab, txt, (int)w0, warm);
-    uint32_t cnt = 0;
+    ChunkOut r = {0, 0, 0};
     u32x4 nx = txt.vec(w0);
-    for (uint32_t v = 0; v < wpc; v += 4) {
-        const u32x4 x4 = nx;
-        if (v + 4 < wpc) nx = txt.vec(w0 + v + 4);
+    for (uint32_t g = 0; g < spc; ++g) {
+        const uint32_t s_entry = s;
+        uint32_t sm = 0;
 #pragma unroll
-        for (uint32_t q = 0; q < 4; ++q) {
-            const uint32_t x = x4[q];
-            const uint32_t s_in = s;
-            uint32_t acc = 0;
+        for (uint32_t v = 0; v < WPS; v += 4) {
+            const u32x4 x4 = nx;
+            const uint32_t wn = g * WPS + v + 4;
+            if (wn < wpc) nx = txt.vec(w0 + wn);
 #pragma unroll
-            for (uint32_t k = 0; k < SPW; ++k) {
-                s = tab(s + sym_bytes<FMT>(x, k));
-                acc = acc > s ? acc : s;
-            }
-            if (acc >= fo) {
-                // rare: walk the word again and add the output-set sizes
-                const uint32_t p0 = (v + q) * SPW;
-                uint32_t r = s_in;
+            for (uint32_t q = 0; q < 4; ++q) {
+                const uint32_t x = x4[q];
+                uint32_t st[SPW];
+                uint32_t acc = 0;
+#pragma unroll
                 for (uint32_t k = 0; k < SPW; ++k) {
-                    r = tab(r + sym_bytes<FMT>(x, k));
-                    if (r >= fo && p0 + k < lim) {
-                        const uint32_t o = row_state(r, tz, inv) - fo_state;
-                        cnt += out_off[o + 1] - out_off[o];
+                    s = tab(s + sym_bytes<FMT>(x, k));
+                    st[k] = s;
+                    acc = acc > s ? acc : s;
+                }
+                if (acc >= fo) {
+                    // some state of this word has an output set: add sizes
+                    const uint32_t p0 = (g * WPS + v + q) * SPW;
+#pragma unroll
+                    for (uint32_t k = 0; k < SPW; ++k) {
+                        if (st[k] >= fo && p0 + k < lim) {
+                            const uint32_t o = row_state(st[k], tz, inv) - fo_state;
+                            sm += out_off[o + 1] - out_off[o];
+                        }
                     }
                 }
             }
         }
+        if (sm) {
+            r.mask |= 1u << g;
+            seg_state[seg0 + g] = s_entry;
+            seg_m[seg0 + g] = sm;
+            r.dense += sm >= kDenseMatches;
+        }
+        r.m += sm;
     }
-    return cnt;
+    return r;
 }
 
 // Copy the LDS part of a table (zero-filled past the table's end).
 __device__ __forceinline__ void load_lds_table(rsrc_t g, uint32_t bytes) {
     extern __shared__ uint32_t dyn_smem[];
     for (uint32_t o = threadIdx.x * 4u; o < bytes; o += blockDim.x * 4u)
-        ((lds_u32 *)dyn_smem)[o >> 2] = __builtin_amdgcn_raw_buffer_load_b32(g, o, 0, 0);
+        ((lds_u32 *)dyn_smem)[o >> 2] = buf_load(g, o);
 }
 
 // Persistent count kernel.  Block b takes a contiguous range of tiles; a
@@ -317,9 +158,12 @@ template <int FMT, bool BATCH>
 __global__ __launch_bounds__(kMaxCountThreads) void k_count(
     Inst single, const Inst *__restrict__ insts, const TileDesc *__restrict__ tiles,
     uint32_t n_tiles, uint32_t chunk, uint32_t warm, uint32_t *__restrict__ cnt,
-    unsigned long long *__restrict__ tile_sum, uint32_t *__restrict__ tile_nz) {
+    uint32_t *__restrict__ mask, uint32_t *__restrict__ seg_state, uint32_t *__restrict__ seg_m,
+    unsigned long long *__restrict__ tile_m, uint32_t *__restrict__ tile_zs,
+    uint32_t *__restrict__ tile_zd) {
     __shared__ unsigned long long red_a[16];
-    __shared__ uint32_t red_b[16];
+    __shared__ uint32_t red_b[16], red_c[16];
+    const uint32_t spc = chunk / kSeg;
     const uint32_t t0 = (uint32_t)(((uint64_t)n_tiles * blockIdx.x) / gridDim.x);
     const uint32_t t1 = (uint32_t)(((uint64_t)n_tiles * (blockIdx.x + 1)) / gridDim.x);
     int cur = -1;
@@ -335,11 +179,10 @@ __global__ __launch_bounds__(kMaxCountThreads) void k_count(
             count = min(blockDim.x, single.n_chunks - first);
         }
         const Inst &I = BATCH ? insts[inst] : single;
-        const uint32_t *delta = uniform(I.delta);
         const uint32_t table_bytes = uniform(I.table_bytes);
         const uint32_t hot = uniform(I.hot_bytes);
         const uint32_t lds_all = uniform(I.lds_all);
-        const rsrc_t gtab = make_rsrc(delta, table_bytes);
+        const rsrc_t gtab = make_rsrc(uniform(I.delta), table_bytes);
         if ((int)inst != cur) {
             if (hot) {
                 __syncthreads();
@@ -349,45 +192,55 @@ __global__ __launch_bounds__(kMaxCountThreads) void k_count(
             cur = (int)inst;
         }
         const uint32_t n = uniform(I.n);
-        const UText txt{make_rsrc(uniform(I.text), uniform(I.text_bytes4)), uniform(I.text_bytes4)};
+        const uint32_t tb4 = uniform(I.text_bytes4);
+        const UText txt{make_rsrc(uniform(I.text), tb4), tb4};
         const uint32_t *out_off = uniform(I.out_off);
         const uint32_t fo = uniform(I.fo_bytes), fos = uniform(I.fo_state);
         const uint32_t tz = uniform(I.div_tz), inv = uniform(I.div_inv);
+        const uint32_t cbase = uniform(I.chunk_base);
         const uint32_t lane_chunk = first + threadIdx.x;
         const bool valid = threadIdx.x < count;
         const uint32_t j = valid ? lane_chunk : first;
         const uint64_t begin = (uint64_t)j * chunk;
         const uint32_t lim = valid ? (uint32_t)min<uint64_t>(chunk, n - begin) : 0u;
-        uint32_t c;
+        const uint32_t seg0 = (cbase + j) * spc;
+        ChunkOut c;
         if (lds_all) {
-            c = walk_count<FMT, PL_LDS>(UTable<PL_LDS>{gtab, hot}, txt, out_off, fo, fos, tz, inv, j,
-                                        chunk, warm, lim);
+            c = walk_count<FMT, PL_LDS>(UTable<PL_LDS>{gtab, hot}, txt, out_off, fo, fos, tz, inv,
+                                        j, chunk, warm, lim, seg_state, seg_m, seg0);
         } else if (hot == 0) {
             c = walk_count<FMT, PL_GLOBAL>(UTable<PL_GLOBAL>{gtab, 0}, txt, out_off, fo, fos, tz,
-                                           inv, j, chunk, warm, lim);
+                                           inv, j, chunk, warm, lim, seg_state, seg_m, seg0);
         } else {
             c = walk_count<FMT, PL_HYBRID>(UTable<PL_HYBRID>{gtab, hot}, txt, out_off, fo, fos, tz,
-                                           inv, j, chunk, warm, lim);
+                                           inv, j, chunk, warm, lim, seg_state, seg_m, seg0);
         }
-        if (valid) cnt[uniform(I.chunk_base) + lane_chunk] = c;
-        // tile totals
-        const unsigned long long ws = wave_sum_u64(c);
-        const uint32_t wz = wave_sum_u32(c != 0);
+        if (valid) {
+            cnt[cbase + lane_chunk] = c.m;
+            mask[cbase + lane_chunk] = c.mask;
+        }
+        // tile totals: matches, sparse and dense segments
+        const uint32_t nz = __builtin_popcount(c.mask);
+        const unsigned long long wa = wave_sum_u64(c.m);
+        const uint32_t wb = wave_sum_u32(nz - c.dense), wc = wave_sum_u32(c.dense);
         const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
         if (lane == 0) {
-            red_a[wid] = ws;
-            red_b[wid] = wz;
+            red_a[wid] = wa;
+            red_b[wid] = wb;
+            red_c[wid] = wc;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
             unsigned long long a = 0;
-            uint32_t b = 0;
+            uint32_t b = 0, d = 0;
             for (uint32_t w = 0; w < (blockDim.x >> 6); ++w) {
                 a += red_a[w];
                 b += red_b[w];
+                d += red_c[w];
             }
-            tile_sum[t] = a;
-            tile_nz[t] = b;
+            tile_m[t] = a;
+            tile_zs[t] = b;
+            tile_zd[t] = d;
         }
         __syncthreads();
     }
@@ -395,82 +248,105 @@ __global__ __launch_bounds__(kMaxCountThreads) void k_count(
 
 // ------------------------------------------------------------------ offsets
 
-// One block: exclusive offsets of the tile sums.  totals[0] = matches,
-// totals[1] = chunks with matches; tile_off[n] / tile_nzoff[n] = totals.
-__global__ __launch_bounds__(1024) void k_tile_scan(const unsigned long long *__restrict__ tile_sum,
-                                                    const uint32_t *__restrict__ tile_nz,
-                                                    uint32_t n, unsigned long long *tile_off,
-                                                    uint32_t *tile_nzoff,
-                                                    unsigned long long *totals,
-                                                    unsigned long long *single_count) {
+// One block: exclusive offsets of the tile totals.  totals[0] = matches,
+// totals[1] = sparse segments, totals[2] = dense segments; entry n of each
+// offset array holds the grand total.
+__global__ __launch_bounds__(1024) void k_tile_scan(
+    const unsigned long long *__restrict__ tile_m, const uint32_t *__restrict__ tile_zs,
+    const uint32_t *__restrict__ tile_zd, uint32_t n, unsigned long long *tile_moff,
+    uint32_t *tile_zsoff, uint32_t *tile_zdoff, unsigned long long *totals,
+    unsigned long long *single_count) {
     const uint32_t per = (n + blockDim.x - 1) / blockDim.x;
     const uint32_t b = min(n, threadIdx.x * per), e = min(n, b + per);
-    unsigned long long sa = 0;
-    uint32_t sb = 0;
+    Scan3 v = {0, 0, 0};
     for (uint32_t i = b; i < e; ++i) {
-        sa += tile_sum[i];
-        sb += tile_nz[i];
+        v.a += tile_m[i];
+        v.b += tile_zs[i];
+        v.c += tile_zd[i];
     }
-    unsigned long long ea, ta;
-    uint32_t eb, tb;
-    block_excl_scan2(sa, sb, &ea, &eb, &ta, &tb);
+    Scan3 ex, tot;
+    block_excl_scan3(v, &ex, &tot);
     for (uint32_t i = b; i < e; ++i) {
-        tile_off[i] = ea;
-        tile_nzoff[i] = eb;
-        ea += tile_sum[i];
-        eb += tile_nz[i];
+        tile_moff[i] = ex.a;
+        tile_zsoff[i] = ex.b;
+        tile_zdoff[i] = ex.c;
+        ex.a += tile_m[i];
+        ex.b += tile_zs[i];
+        ex.c += tile_zd[i];
     }
     if (threadIdx.x == 0) {
-        tile_off[n] = ta;
-        tile_nzoff[n] = tb;
-        totals[0] = ta;
-        totals[1] = tb;
-        if (single_count) *single_count = ta;
+        tile_moff[n] = tot.a;
+        tile_zsoff[n] = tot.b;
+        tile_zdoff[n] = tot.c;
+        totals[0] = tot.a;
+        totals[1] = tot.b;
+        totals[2] = tot.c;
+        if (single_count) *single_count = tot.a;
     }
 }
 
-// One block per tile: output offset of every chunk with matches, appended
-// to the work list of k_emit in text order.
+// One block per tile: append every segment with matches to the work list,
+// with its entry state and the offset of its first match (relative to its
+// instance's output).  Sparse segments fill the list from the front in text
+// order, dense ones follow all sparse ones, also in text order.
 template <bool BATCH>
 __global__ __launch_bounds__(kMaxCountThreads) void k_scatter(
     Inst single, const Inst *__restrict__ insts, const TileDesc *__restrict__ tiles,
-    const uint32_t *__restrict__ cnt, const unsigned long long *__restrict__ tile_off,
-    const uint32_t *__restrict__ tile_nzoff, uint32_t *__restrict__ list_chunk,
-    uint32_t *__restrict__ list_inst, unsigned long long *__restrict__ list_off) {
+    uint32_t chunk, const uint32_t *__restrict__ cnt, const uint32_t *__restrict__ mask,
+    const uint32_t *__restrict__ seg_state, const uint32_t *__restrict__ seg_m,
+    const unsigned long long *__restrict__ tile_moff, const uint32_t *__restrict__ tile_zsoff,
+    const uint32_t *__restrict__ tile_zdoff, const unsigned long long *__restrict__ totals,
+    uint32_t *__restrict__ list_seg, uint32_t *__restrict__ list_state,
+    unsigned long long *__restrict__ list_moff, uint32_t *__restrict__ list_inst) {
     const uint32_t t = blockIdx.x;
-    uint32_t inst = 0, first, count, chunk_base = 0;
+    const uint32_t spc = chunk / kSeg;
+    uint32_t inst = 0, first, count, cbase = 0;
     unsigned long long base_off = 0;
     if constexpr (BATCH) {
         const TileDesc td = tiles[t];
         inst = td.inst;
         first = td.first;
         count = td.count;
-        chunk_base = insts[inst].chunk_base;
-        base_off = tile_off[insts[inst].first_tile];
+        cbase = insts[inst].chunk_base;
+        base_off = tile_moff[insts[inst].first_tile];
     } else {
         first = t * blockDim.x;
         count = min(blockDim.x, single.n_chunks - first);
     }
     const bool valid = threadIdx.x < count;
     const uint32_t j = first + threadIdx.x;
-    const uint32_t c = valid ? cnt[chunk_base + j] : 0u;
-    unsigned long long ea, ta;
-    uint32_t eb, tb;
-    block_excl_scan2(c, c != 0, &ea, &eb, &ta, &tb);
-    if (c != 0) {
-        const uint32_t k = tile_nzoff[t] + eb;
-        list_chunk[k] = j;
+    const uint32_t g = cbase + j;
+    const uint32_t m = valid ? cnt[g] : 0u;
+    const uint32_t mk = valid ? mask[g] : 0u;
+    uint32_t zd = 0;
+    for (uint32_t b = mk; b; b &= b - 1)
+        zd += seg_m[g * spc + __builtin_ctz(b)] >= kDenseMatches;
+    const uint32_t zs = __builtin_popcount(mk) - zd;
+    Scan3 ex, tot;
+    block_excl_scan3(Scan3{m, zs, zd}, &ex, &tot);
+    const uint32_t n_sparse = (uint32_t)totals[1];
+    uint32_t ks = tile_zsoff[t] + ex.b;
+    uint32_t kd = n_sparse + tile_zdoff[t] + ex.c;
+    unsigned long long off = tile_moff[t] + ex.a - base_off;
+    for (uint32_t b = mk; b; b &= b - 1) {
+        const uint32_t i = __builtin_ctz(b);
+        const uint32_t gs = g * spc + i;
+        const uint32_t sm = seg_m[gs];
+        const uint32_t k = sm >= kDenseMatches ? kd++ : ks++;
+        list_seg[k] = j * spc + i;
+        list_state[k] = seg_state[gs];
+        list_moff[k] = off;
         if constexpr (BATCH) list_inst[k] = inst;
-        list_off[k] = tile_off[t] + ea - base_off;
+        off += sm;
     }
 }
 
 __global__ void k_inst_totals(const Inst *__restrict__ insts, uint32_t n_inst,
-                              const unsigned long long *__restrict__ tile_off) {
+                              const unsigned long long *__restrict__ tile_moff) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_inst) return;
     const Inst &I = insts[i];
-    *I.count = tile_off[I.first_tile + I.n_tiles] - tile_off[I.first_tile];
+    *I.count = tile_moff[I.first_tile + I.n_tiles] - tile_moff[I.first_tile];
 }
 
 __global__ void k_fill_u64(unsigned long long *p, uint32_t n, unsigned long long v) {
@@ -480,90 +356,78 @@ __global__ void k_fill_u64(unsigned long long *p, uint32_t n, unsigned long long
 
 // ------------------------------------------------------------------ emit
 
-// Per-wave record table for cooperative writing of output sets.
-struct WaveRecs {
-    uint32_t incl[64];   // inclusive prefix of output-set sizes
-    uint32_t ids[64];    // first index of the set in out_ids
-    uint32_t end[64];    // end position
-    uint32_t inst[64];   // instance (batched form)
-    unsigned long long off[64];  // output offset of the set's first match
-};
-
-// All lanes of the wave call this with `has` set where the lane's state
-// (row offset e) is an output state at text position pos.  The wave then
-// writes all the matches of all these states together: item k of the
-// concatenated sets goes to lane k % 64, so consecutive lanes write
-// consecutive 8-byte slots of the output.
-template <bool BATCH>
-__device__ __forceinline__ void emit_sets(WaveRecs &R, bool has, uint32_t e, uint32_t pos,
-                                          unsigned long long &off, uint32_t inst,
-                                          const Inst &I0, const Inst *__restrict__ insts,
-                                          const uint32_t *out_off, uint32_t fo_state, uint32_t tz,
-                                          uint32_t inv) {
-    const uint32_t lane = threadIdx.x & 63;
-    uint32_t len = 0, first = 0;
-    if (has) {
-        const uint32_t o = row_state(e, tz, inv) - fo_state;
-        first = out_off[o];
-        len = out_off[o + 1] - first;
-    }
-    const uint32_t incl = wave_incl_scan(len);
-    const uint32_t total = __shfl(incl, 63, 64);
-    R.incl[lane] = incl;
-    R.ids[lane] = first;
-    R.end[lane] = pos;
-    R.off[lane] = off;
-    if constexpr (BATCH) R.inst[lane] = inst;
-    off += len;
-    wave_sync();
-    for (uint32_t k = lane; k < total; k += 64) {
-        uint32_t r = 0;
+// Write the output set ids[a .. a+len) of a state entered at end position e
+// into out[off ..], skipping slots >= cap.  Ids are fetched 16 at a time so
+// that one memory latency covers 16 matches.
+__device__ __forceinline__ void write_set(ac_match *__restrict__ out, unsigned long long off,
+                                          unsigned long long cap,
+                                          const uint32_t *__restrict__ ids, uint32_t a,
+                                          uint32_t len, uint32_t e) {
+    constexpr uint32_t B = 16;
+    for (uint32_t i = 0; i < len; i += B) {
+        uint32_t v[B];
 #pragma unroll
-        for (uint32_t step = 32; step > 0; step >>= 1)
-            if (R.incl[r + step - 1] <= k) r += step;
-        const uint32_t excl = r ? R.incl[r - 1] : 0u;
-        const uint32_t idx = k - excl;
-        const unsigned long long dst = R.off[r] + idx;
-        const Inst &I = BATCH ? insts[R.inst[r]] : I0;
-        if (dst < I.capacity) {
-            ac_match m;
-            m.pattern_id = I.out_ids[R.ids[r] + idx];
-            m.end_pos = R.end[r];
-            I.out[dst] = m;
+        for (uint32_t u = 0; u < B; ++u) v[u] = (i + u < len) ? ids[a + i + u] : 0u;
+#pragma unroll
+        for (uint32_t u = 0; u < B; ++u) {
+            const unsigned long long d = off + i + u;
+            if (i + u < len && d < cap) {
+                ac_match m;
+                m.pattern_id = v[u];
+                m.end_pos = e;
+                out[d] = m;
+            }
         }
     }
-    wave_sync();
 }
 
-// Persistent emit kernel over the list of chunks with matches.
+// Sparse part of the work list: one lane per listed segment walks its 64
+// symbols from the stored entry state and writes the output set of every
+// state it enters, in id order, at consecutive slots from the segment's
+// first slot.
+//
+// Stores are kept out of the walk: on gfx9 a wave's wait for a load also
+// waits for its earlier stores, so a store in the middle of the dependent
+// lookup chain would stall every later step.  The walk therefore records up
+// to kEvents output events (state, position) per lane in LDS, and the
+// writes follow the walk.  A word that reaches an output state is walked a
+// second time to record its events, so the common word costs one lookup per
+// symbol and a max.  Lanes with more than kEvents events walk the segment a
+// second time for the rest (rare: a segment listed as sparse has fewer than
+// kDenseMatches matches).
+constexpr uint32_t kEvents = 16;
+
 template <int FMT, bool BATCH>
 __global__ __launch_bounds__(kEmitThreads) void k_emit(
-    Inst single, const Inst *__restrict__ insts, uint32_t chunk, uint32_t warm,
-    const uint32_t *__restrict__ list_chunk, const uint32_t *__restrict__ list_inst,
-    const unsigned long long *__restrict__ list_off, const unsigned long long *__restrict__ totals) {
+    Inst single, const Inst *__restrict__ insts, const uint32_t *__restrict__ list_seg,
+    const uint32_t *__restrict__ list_state, const unsigned long long *__restrict__ list_moff,
+    const uint32_t *__restrict__ list_inst, const unsigned long long *__restrict__ totals) {
     constexpr uint32_t SPW = Fmt<FMT>::SPW;
-    __shared__ WaveRecs recs[kEmitThreads / 64];
-    WaveRecs &R = recs[threadIdx.x >> 6];
-    const uint32_t nz = (uint32_t)totals[1];
-    const uint32_t wpc = chunk / SPW;
-    for (uint32_t base = blockIdx.x * blockDim.x; base < nz; base += gridDim.x * blockDim.x) {
-        const uint32_t idx = base + threadIdx.x;
-        const bool valid = idx < nz;
-        const uint32_t j = valid ? list_chunk[idx] : 0u;
-        uint32_t inst = 0;
-        if constexpr (BATCH) inst = valid ? list_inst[idx] : 0u;
-        unsigned long long off = valid ? list_off[idx] : 0ull;
+    constexpr uint32_t WPS = kSeg / SPW;
+    __shared__ uint32_t ev_state[kEvents][kEmitThreads];
+    __shared__ uint8_t ev_pos[kEvents][kEmitThreads];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t total = (uint32_t)totals[1];
+    for (uint32_t idx = blockIdx.x * blockDim.x + tid; idx < total;
+         idx += gridDim.x * blockDim.x) {
+        const uint32_t inst = BATCH ? list_inst[idx] : 0u;
         const Inst &I = BATCH ? insts[inst] : single;
-        const uint32_t n = I.n;
-        const uint64_t begin = (uint64_t)j * chunk;
-        const uint32_t lim = valid ? (uint32_t)min<uint64_t>(chunk, n - begin) : 0u;
+        const uint32_t seg = list_seg[idx];
+        const uint32_t s0 = list_state[idx];
+        const unsigned long long off0 = list_moff[idx];
+        const uint32_t e0 = seg * kSeg;
+        const uint32_t lim = min(kSeg, I.n - e0);
         const uint32_t fo = I.fo_bytes, fos = I.fo_state, tz = I.div_tz, inv = I.div_inv;
         const uint32_t *out_off = I.out_off;
-        const uint32_t w0 = j * wpc;
+        const uint32_t *ids = I.out_ids;
+        ac_match *out = I.out;
+        const unsigned long long cap = I.capacity;
         auto body = [&](const auto &tab, const auto &txt) {
-            uint32_t s = warm_up<FMT>(tab, txt, (int)w0, warm);
-            for (uint32_t w = 0; w < wpc; ++w) {
-                const uint32_t x = txt.word((int)(w0 + w));
+            // walk, recording output events
+            uint32_t s = s0, ne = 0;
+#pragma unroll 1
+            for (uint32_t w = 0; w < WPS; ++w) {
+                const uint32_t x = txt.word((int)(seg * WPS + w));
                 const uint32_t s_in = s;
                 uint32_t acc = 0;
 #pragma unroll
@@ -571,27 +435,154 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
                     s = tab(s + sym_bytes<FMT>(x, k));
                     acc = acc > s ? acc : s;
                 }
-                if (__any(acc >= fo && lim > 0)) {
-                    const uint32_t p0 = w * SPW;
-                    uint32_t r = s_in;
-                    for (uint32_t k = 0; k < SPW; ++k) {
-                        r = tab(r + sym_bytes<FMT>(x, k));
-                        const bool has = r >= fo && p0 + k < lim;
-                        if (__any(has))
-                            emit_sets<BATCH>(R, has, r, (uint32_t)(begin + p0 + k), off, inst,
-                                             single, insts, out_off, fos, tz, inv);
+                if (acc < fo) continue;
+                uint32_t r = s_in;
+#pragma unroll 1
+                for (uint32_t k = 0; k < SPW; ++k) {
+                    r = tab(r + sym_bytes<FMT>(x, k));
+                    const uint32_t p = w * SPW + k;
+                    if (r >= fo && p < lim) {
+                        if (ne < kEvents) {
+                            ev_state[ne][tid] = r;
+                            ev_pos[ne][tid] = (uint8_t)p;
+                        }
+                        ++ne;
                     }
+                }
+            }
+            // write the recorded events
+            unsigned long long off = off0;
+            const uint32_t nrec = ne < kEvents ? ne : kEvents;
+            for (uint32_t j = 0; j < nrec; ++j) {
+                const uint32_t r = ev_state[j][tid];
+                const uint32_t p = ev_pos[j][tid];
+                const uint32_t o = row_state(r, tz, inv) - fos;
+                const uint32_t a = out_off[o], len = out_off[o + 1] - a;
+                write_set(out, off, cap, ids, a, len, e0 + p);
+                off += len;
+            }
+            if (ne <= kEvents) return;
+            // more events than recorded: walk again, writing from event kEvents on
+            uint32_t t = s0, seen = 0;
+#pragma unroll 1
+            for (uint32_t p = 0; p < lim; ++p) {
+                const uint32_t x = txt.word((int)(seg * WPS + p / SPW));
+                t = tab(t + sym_bytes<FMT>(x, p % SPW));
+                if (t >= fo) {
+                    if (seen >= kEvents) {
+                        const uint32_t o = row_state(t, tz, inv) - fos;
+                        const uint32_t a = out_off[o], len = out_off[o + 1] - a;
+                        write_set(out, off, cap, ids, a, len, e0 + p);
+                        off += len;
+                    }
+                    ++seen;
                 }
             }
         };
         if constexpr (BATCH) {
-            LTable tab{I.delta, I.table_bytes};
-            LText txt{(const uint32_t *)I.text, I.text_bytes4};
-            body(tab, txt);
+            body(LTable{I.delta, I.table_bytes}, LText{(const uint32_t *)I.text, I.text_bytes4});
         } else {
-            UTable<PL_GLOBAL> tab{make_rsrc(single.delta, single.table_bytes), 0};
-            UText txt{make_rsrc(single.text, single.text_bytes4), single.text_bytes4};
-            body(tab, txt);
+            body(UTable<PL_GLOBAL>{make_rsrc(single.delta, single.table_bytes), 0},
+                 UText{make_rsrc(single.text, single.text_bytes4), single.text_bytes4});
+        }
+    }
+}
+
+// Dense part of the work list: one wave per listed segment.  The wave walks
+// the segment once (all lanes together, so every lookup is one broadcast
+// read); lane k keeps the state entered at position k.  A prefix sum of the
+// output-set sizes over the wave gives each position its first slot.  The
+// positions are then written one after the other, each by the whole wave:
+// lane i writes match i of the set, so every store instruction covers 64
+// consecutive 8-byte slots.  The ids of the last set written stay in
+// registers, so a run of positions in the same state (a poly-A run, say)
+// loads them once.
+template <int FMT, bool BATCH>
+__global__ __launch_bounds__(kEmitThreads) void k_emit_dense(
+    Inst single, const Inst *__restrict__ insts, const uint32_t *__restrict__ list_seg,
+    const uint32_t *__restrict__ list_state, const unsigned long long *__restrict__ list_moff,
+    const uint32_t *__restrict__ list_inst, const unsigned long long *__restrict__ totals) {
+    constexpr uint32_t SPW = Fmt<FMT>::SPW;
+    constexpr uint32_t WPS = kSeg / SPW;
+    const uint32_t n_sparse = (uint32_t)totals[1];
+    const uint32_t n_dense = (uint32_t)totals[2];
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+    for (uint32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < n_dense;
+         w += waves) {
+        const uint32_t idx = n_sparse + w;
+        const uint32_t inst = BATCH ? uniform(list_inst[idx]) : 0u;
+        const Inst &I = BATCH ? insts[inst] : single;
+        const uint32_t seg = uniform(list_seg[idx]);
+        uint32_t s = uniform(list_state[idx]);
+        const unsigned long long off0 = uniform(list_moff[idx]);
+        const uint32_t e0 = seg * kSeg;
+        const uint32_t lim = min(kSeg, uniform(I.n) - e0);
+        const uint32_t fo = uniform(I.fo_bytes), fos = uniform(I.fo_state);
+        const uint32_t tz = uniform(I.div_tz), inv = uniform(I.div_inv);
+        const uint32_t tb = uniform(I.table_bytes), tb4 = uniform(I.text_bytes4);
+        const uint32_t *out_off = uniform(I.out_off);
+        const uint32_t *ids = uniform(I.out_ids);
+        ac_match *out = uniform(I.out);
+        const unsigned long long cap = uniform(I.capacity);
+        const UTable<PL_GLOBAL> tab{make_rsrc(uniform(I.delta), tb), 0};
+        const UText txt{make_rsrc(uniform(I.text), tb4), tb4};
+        uint32_t mine = 0;
+#pragma unroll
+        for (uint32_t v = 0; v < WPS; v += 4) {
+            const u32x4 x4 = txt.vec(seg * WPS + v);
+#pragma unroll
+            for (uint32_t q = 0; q < 4; ++q) {
+#pragma unroll
+                for (uint32_t k = 0; k < SPW; ++k) {
+                    s = tab(s + sym_bytes<FMT>(x4[q], k));
+                    if (lane == (v + q) * SPW + k) mine = s;
+                }
+            }
+        }
+        uint32_t a = 0, len = 0;
+        if (mine >= fo && lane < lim) {
+            const uint32_t o = row_state(mine, tz, inv) - fos;
+            a = out_off[o];
+            len = out_off[o + 1] - a;
+        }
+        const uint32_t excl = wave_incl_scan(len) - len;
+        uint64_t todo = __ballot(len != 0);
+        uint32_t cur = 0xFFFFFFFFu, v0 = 0, v1 = 0;
+        while (todo) {
+            const uint32_t k = (uint32_t)__builtin_ctzll(todo);
+            todo &= todo - 1;
+            const uint32_t ka = __builtin_amdgcn_readlane(a, k);
+            const uint32_t kl = __builtin_amdgcn_readlane(len, k);
+            const unsigned long long ko = off0 + __builtin_amdgcn_readlane(excl, k);
+            if (ko >= cap) break;
+            const uint32_t e = e0 + k;
+            if (kl <= 128) {
+                if (ka != cur) {
+                    v0 = lane < kl ? ids[ka + lane] : 0u;
+                    v1 = lane + 64 < kl ? ids[ka + 64 + lane] : 0u;
+                    cur = ka;
+                }
+                if (lane < kl && ko + lane < cap) {
+                    ac_match m;
+                    m.pattern_id = v0;
+                    m.end_pos = e;
+                    out[ko + lane] = m;
+                }
+                if (lane + 64 < kl && ko + 64 + lane < cap) {
+                    ac_match m;
+                    m.pattern_id = v1;
+                    m.end_pos = e;
+                    out[ko + 64 + lane] = m;
+                }
+            } else {
+                for (uint32_t i = lane; i < kl && ko + i < cap; i += 64) {
+                    ac_match m;
+                    m.pattern_id = ids[ka + i];
+                    m.end_pos = e;
+                    out[ko + i] = m;
+                }
+            }
         }
     }
 }
@@ -758,6 +749,54 @@ void release_dict(ac_dict *d) {
     (void)hipGetLastError();
 }
 
+// ---------------------------------------------------------- kernel timing
+
+struct TimedPair {
+    int kind;
+    hipEvent_t a, b;
+};
+static std::mutex g_tm_mu;
+static bool g_tm_on = false;
+static std::vector<TimedPair> g_tm_pending;
+static std::vector<hipEvent_t> g_tm_free;
+static double g_tm_ms[AC_K_KINDS];
+static uint64_t g_tm_n[AC_K_KINDS];
+
+static hipEvent_t tm_event() {
+    if (!g_tm_free.empty()) {
+        hipEvent_t e = g_tm_free.back();
+        g_tm_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+// Records an event pair around one kernel launch when timing is enabled.
+struct KTimer {
+    int kind;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    KTimer(int k, hipStream_t s) : kind(k), st(s) {
+        std::lock_guard<std::mutex> lk(g_tm_mu);
+        if (!g_tm_on) return;
+        a = tm_event();
+        if (a) (void)hipEventRecord(a, st);
+    }
+    ~KTimer() {
+        if (!a) return;
+        std::lock_guard<std::mutex> lk(g_tm_mu);
+        hipEvent_t b = tm_event();
+        if (!b) return;
+        (void)hipEventRecord(b, st);
+        g_tm_pending.push_back({kind, a, b});
+    }
+};
+
 // ---------------------------------------------------------- launch geometry
 
 static uint32_t spw_of(uint32_t fmt) { return fmt == AC_TEXT_2BIT ? 16u : 4u; }
@@ -765,41 +804,49 @@ static uint32_t spw_of(uint32_t fmt) { return fmt == AC_TEXT_2BIT ? 16u : 4u; }
 static uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
 struct Geom {
-    uint32_t chunk = 0, threads = 0, warm = 0, grid_count = 0, grid_emit = 0;
+    uint32_t chunk = 0, threads = 0, warm = 0, grid_count = 0;
+    uint32_t grid_emit = 0, grid_dense = 0;  // bounded by the largest possible work list
     uint32_t lds_bytes = 0;  // dynamic LDS of k_count
     uint64_t n_chunks = 0, n_tiles = 0;
+    uint64_t n_segs() const { return n_chunks * (chunk / kSeg); }
 };
 
 struct Workspace {
-    uint32_t *cnt;
-    unsigned long long *tile_sum;
-    uint32_t *tile_nz;
-    unsigned long long *tile_off;
-    uint32_t *tile_nzoff;
-    unsigned long long *totals;
-    uint32_t *list_chunk;
-    uint32_t *list_inst;
-    unsigned long long *list_off;
+    uint32_t *cnt, *mask;                 // per chunk
+    uint32_t *seg_state, *seg_m;          // per segment (written where matches exist)
+    unsigned long long *tile_m;           // per tile
+    uint32_t *tile_zs, *tile_zd;
+    unsigned long long *tile_moff;        // per tile, + grand total
+    uint32_t *tile_zsoff, *tile_zdoff;
+    unsigned long long *totals;           // matches, sparse segments, dense segments
+    uint32_t *list_seg, *list_state, *list_inst;  // work list of segments
+    unsigned long long *list_moff;
 };
 
-static uint64_t ws_layout(uint64_t n_chunks, uint64_t n_tiles, bool batch, char *base,
-                          Workspace *w) {
+static uint64_t ws_layout(const Geom &g, bool batch, char *base, Workspace *w) {
     uint64_t o = 0;
     auto take = [&](uint64_t bytes) {
         char *p = base ? base + o : nullptr;
         o += align256(std::max<uint64_t>(bytes, 8));
         return p;
     };
+    const uint64_t C = g.n_chunks, T = g.n_tiles, S = g.n_segs();
     Workspace t;
-    t.cnt = (uint32_t *)take(4 * n_chunks);
-    t.tile_sum = (unsigned long long *)take(8 * n_tiles);
-    t.tile_nz = (uint32_t *)take(4 * n_tiles);
-    t.tile_off = (unsigned long long *)take(8 * (n_tiles + 1));
-    t.tile_nzoff = (uint32_t *)take(4 * (n_tiles + 1));
-    t.totals = (unsigned long long *)take(16);
-    t.list_chunk = (uint32_t *)take(4 * n_chunks);
-    t.list_inst = batch ? (uint32_t *)take(4 * n_chunks) : nullptr;
-    t.list_off = (unsigned long long *)take(8 * n_chunks);
+    t.cnt = (uint32_t *)take(4 * C);
+    t.mask = (uint32_t *)take(4 * C);
+    t.seg_state = (uint32_t *)take(4 * S);
+    t.seg_m = (uint32_t *)take(4 * S);
+    t.tile_m = (unsigned long long *)take(8 * T);
+    t.tile_zs = (uint32_t *)take(4 * T);
+    t.tile_zd = (uint32_t *)take(4 * T);
+    t.tile_moff = (unsigned long long *)take(8 * (T + 1));
+    t.tile_zsoff = (uint32_t *)take(4 * (T + 1));
+    t.tile_zdoff = (uint32_t *)take(4 * (T + 1));
+    t.totals = (unsigned long long *)take(32);
+    t.list_seg = (uint32_t *)take(4 * S);
+    t.list_state = (uint32_t *)take(4 * S);
+    t.list_inst = batch ? (uint32_t *)take(4 * S) : nullptr;
+    t.list_moff = (unsigned long long *)take(8 * S);
     if (w) *w = t;
     return o;
 }
@@ -811,7 +858,7 @@ static void choose_placement(const ac_dict *d, uint32_t requested, uint32_t lds_
     const uint32_t row = d->host.sigma * 4u;
     uint32_t p = requested ? requested : d->placement;
     const bool fits = tb + kLdsPad <= lds_limit;
-    if (p == AC_PLACE_AUTO) p = fits ? AC_PLACE_LDS : AC_PLACE_GLOBAL;
+    if (p == AC_PLACE_AUTO) p = fits ? AC_PLACE_LDS : AC_PLACE_HYBRID;
     if (p == AC_PLACE_LDS && !fits) p = AC_PLACE_HYBRID;
     if (p == AC_PLACE_LDS) {
         *hot = tb;
@@ -834,19 +881,24 @@ static int resolve_geom(const ac_dict *const *dicts, const uint64_t *ns, uint32_
     int rc = device_limits(&cus, &lds);
     if (rc != AC_OK) return rc;
     const uint32_t lds_limit = lds - 512;  // static LDS of the count kernel
-    uint32_t max_len = 1;
-    uint64_t total = 0, biggest = 0;
+    uint32_t max_len = 1, max_out = 1;
+    uint64_t total = 0;
     for (uint32_t i = 0; i < n_inst; ++i) {
         max_len = std::max(max_len, dicts[i]->host.max_len);
+        max_out = std::max(max_out, dicts[i]->host.max_output);
         total += ns[i];
-        biggest = std::max(biggest, ns[i]);
     }
+    // per-chunk match counts are 32-bit
+    if ((uint64_t)kSeg * max_out >= (1ull << 32)) return AC_E_TOO_LARGE;
+    uint32_t max_chunk = kMaxChunk;
+    while ((uint64_t)max_chunk * max_out >= (1ull << 32)) max_chunk /= 2;
     const uint32_t spw = spw_of(fmt);
     g->warm = (max_len - 1 + spw - 1) / spw;
     g->threads = (tune && tune->block_threads) ? tune->block_threads : 1024u;
     if (g->threads < 64 || g->threads > kMaxCountThreads || g->threads % 64) return AC_E_INVALID;
     uint32_t chunk = tune ? tune->chunk : 0;
-    if (chunk && (chunk % 64 || chunk > (1u << 20))) return AC_E_INVALID;
+    if (chunk && (chunk % kSeg || chunk > kMaxChunk)) return AC_E_INVALID;
+    if (chunk > max_chunk) return AC_E_TOO_LARGE;
     // LDS need of the count kernel
     uint32_t lds_bytes = 0;
     const uint32_t req = tune ? tune->placement : 0;
@@ -862,8 +914,8 @@ static int resolve_geom(const ac_dict *const *dicts, const uint64_t *ns, uint32_
     if (lds_bytes) bpc = std::max(1u, std::min(bpc, (lds + 0u) / (lds_bytes + 512u)));
     const uint64_t slots = (uint64_t)cus * bpc;
     if (!chunk) {
-        chunk = 1024;
-        while (chunk > 64 && (total / chunk) / g->threads < slots) chunk /= 2;
+        chunk = std::min<uint32_t>(1024, max_chunk);
+        while (chunk > kSeg && (total / chunk) / g->threads < slots) chunk /= 2;
     }
     g->chunk = chunk;
     g->n_chunks = 0;
@@ -875,7 +927,12 @@ static int resolve_geom(const ac_dict *const *dicts, const uint64_t *ns, uint32_
     }
     if (g->n_chunks >= (1ull << 31) || g->n_tiles >= (1ull << 31)) return AC_E_TOO_LARGE;
     g->grid_count = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g->n_tiles, slots));
-    g->grid_emit = cus * 8;
+    // persistent emit grids, no larger than the work list can ever need
+    const uint64_t segs = g->n_segs();
+    g->grid_emit = (uint32_t)std::max<uint64_t>(
+        1, std::min<uint64_t>((uint64_t)cus * 8, (segs + kEmitThreads - 1) / kEmitThreads));
+    g->grid_dense = (uint32_t)std::max<uint64_t>(
+        1, std::min<uint64_t>((uint64_t)cus * 8, (segs + kEmitThreads / 64 - 1) / (kEmitThreads / 64)));
     return AC_OK;
 }
 
@@ -927,14 +984,36 @@ static int launch_single(const Geom &g, const Inst &I, const Workspace &w, hipSt
     auto kc = k_count<FMT, false>;
     int rc = allow_lds(kc, g.lds_bytes);
     if (rc) return rc;
-    hipLaunchKernelGGL(kc, dim3(g.grid_count), dim3(g.threads), g.lds_bytes, st, I, nullptr,
-                       nullptr, T, g.chunk, g.warm, w.cnt, w.tile_sum, w.tile_nz);
-    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, w.tile_sum, w.tile_nz, T,
-                       w.tile_off, w.tile_nzoff, w.totals, I.count);
-    hipLaunchKernelGGL(k_scatter<false>, dim3(T), dim3(g.threads), 0, st, I, nullptr, nullptr,
-                       w.cnt, w.tile_off, w.tile_nzoff, w.list_chunk, nullptr, w.list_off);
-    hipLaunchKernelGGL((k_emit<FMT, false>), dim3(g.grid_emit), dim3(kEmitThreads), 0, st, I,
-                       nullptr, g.chunk, g.warm, w.list_chunk, nullptr, w.list_off, w.totals);
+    {
+        KTimer tm(AC_K_COUNT, st);
+        hipLaunchKernelGGL(kc, dim3(g.grid_count), dim3(g.threads), g.lds_bytes, st, I, nullptr,
+                           nullptr, T, g.chunk, g.warm, w.cnt, w.mask, w.seg_state, w.seg_m,
+                           w.tile_m, w.tile_zs, w.tile_zd);
+    }
+    {
+        KTimer tm(AC_K_OFFSETS, st);
+        hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, w.tile_m, w.tile_zs,
+                           w.tile_zd, T, w.tile_moff, w.tile_zsoff, w.tile_zdoff, w.totals,
+                           I.count);
+    }
+    {
+        KTimer tm(AC_K_SCATTER, st);
+        hipLaunchKernelGGL(k_scatter<false>, dim3(T), dim3(g.threads), 0, st, I, nullptr, nullptr,
+                           g.chunk, w.cnt, w.mask, w.seg_state, w.seg_m, w.tile_moff,
+                           w.tile_zsoff, w.tile_zdoff, w.totals, w.list_seg, w.list_state,
+                           w.list_moff, nullptr);
+    }
+    {
+        KTimer tm(AC_K_EMIT, st);
+        hipLaunchKernelGGL((k_emit<FMT, false>), dim3(g.grid_emit), dim3(kEmitThreads), 0, st, I,
+                           nullptr, w.list_seg, w.list_state, w.list_moff, nullptr, w.totals);
+    }
+    {
+        KTimer tm(AC_K_EMIT_DENSE, st);
+        hipLaunchKernelGGL((k_emit_dense<FMT, false>), dim3(g.grid_dense), dim3(kEmitThreads), 0,
+                           st, I, nullptr, w.list_seg, w.list_state, w.list_moff, nullptr,
+                           w.totals);
+    }
     HIP_OK(hipGetLastError());
     return AC_OK;
 }
@@ -949,6 +1028,49 @@ int ac_device_info(uint32_t *compute_units, uint32_t *lds_bytes_per_block) {
     return device_limits(compute_units, lds_bytes_per_block);
 }
 
+int ac_timing_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_tm_mu);
+    g_tm_on = on != 0;
+    return AC_OK;
+}
+
+int ac_timing_read(double *ms, uint64_t *launches, int reset) {
+    std::vector<TimedPair> pend;
+    {
+        std::lock_guard<std::mutex> lk(g_tm_mu);
+        pend.swap(g_tm_pending);
+    }
+    int rc = AC_OK;
+    double add[AC_K_KINDS] = {0};
+    uint64_t cnt[AC_K_KINDS] = {0};
+    for (const TimedPair &p : pend) {
+        float t = 0.f;
+        if (hipEventSynchronize(p.b) != hipSuccess || hipEventElapsedTime(&t, p.a, p.b) != hipSuccess) {
+            (void)hipGetLastError();
+            rc = AC_E_HIP;
+        } else {
+            add[p.kind] += t;
+            cnt[p.kind] += 1;
+        }
+    }
+    std::lock_guard<std::mutex> lk(g_tm_mu);
+    for (const TimedPair &p : pend) {
+        g_tm_free.push_back(p.a);
+        g_tm_free.push_back(p.b);
+    }
+    for (int k = 0; k < AC_K_KINDS; ++k) {
+        g_tm_ms[k] += add[k];
+        g_tm_n[k] += cnt[k];
+        if (ms) ms[k] = g_tm_ms[k];
+        if (launches) launches[k] = g_tm_n[k];
+        if (reset) {
+            g_tm_ms[k] = 0;
+            g_tm_n[k] = 0;
+        }
+    }
+    return rc;
+}
+
 int ac_scan_workspace_size(const ac_dict *d, uint64_t n, uint32_t fmt, const ac_tune *tune,
                            uint64_t *bytes) {
     if (!d || !bytes) return AC_E_INVALID;
@@ -957,7 +1079,7 @@ int ac_scan_workspace_size(const ac_dict *d, uint64_t n, uint32_t fmt, const ac_
     Geom g;
     rc = resolve_geom(&d, &n, 1, fmt, tune, &g);
     if (rc) return rc;
-    *bytes = ws_layout(g.n_chunks, g.n_tiles, false, nullptr, nullptr);
+    *bytes = ws_layout(g, false, nullptr, nullptr);
     return AC_OK;
 }
 
@@ -986,7 +1108,7 @@ int ac_scan(const ac_dict *d, const void *d_text, uint64_t n, uint32_t fmt, ac_m
               &I);
     I.n_chunks = (uint32_t)g.n_chunks;
     I.n_tiles = (uint32_t)g.n_tiles;
-    const uint64_t need = ws_layout(g.n_chunks, g.n_tiles, false, nullptr, nullptr);
+    const uint64_t need = ws_layout(g, false, nullptr, nullptr);
     char *ws = (char *)d_workspace;
     bool own = false;
     if (ws) {
@@ -999,7 +1121,7 @@ int ac_scan(const ac_dict *d, const void *d_text, uint64_t n, uint32_t fmt, ac_m
         own = true;
     }
     Workspace w;
-    ws_layout(g.n_chunks, g.n_tiles, false, ws, &w);
+    ws_layout(g, false, ws, &w);
     rc = fmt == AC_TEXT_2BIT ? launch_single<AC_TEXT_2BIT>(g, I, w, st)
                              : launch_single<AC_TEXT_U8>(g, I, w, st);
     if (own) (void)hipFreeAsync(ws, st);
@@ -1016,6 +1138,7 @@ int ac_encode(const uint8_t *d_ascii, uint64_t n, uint32_t alphabet, uint32_t fm
     unsigned long long *inv = (unsigned long long *)d_invalid;
     if (inv) hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, inv, 1u, 0ull);
     if (n) {
+        KTimer tm(AC_K_ENCODE, st);
         const uint64_t threads = (n + 15) / 16;
         const uint32_t blocks = (uint32_t)((threads + 255) / 256);
         const uint8_t *in = d_ascii;

@@ -247,3 +247,19 @@ def test_dna_dense_full():
     got, total = gpu_keys(d, t, len(inst.text), ac.AC_TEXT_2BIT, capacity=len(want) + 1024)
     assert total == len(want)
     assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("pats,n", [
+    ([[0]], 1000),                       # 64 events per segment, 64 matches: sparse, > 16 events
+    ([[0], [0, 0]], 1000),               # 127 matches per segment: sparse
+    ([[0], [0], [0], [0]], 1000),        # exactly 256 matches per full segment: dense
+    ([[0], [0], [0], [0], [0, 0]], 777),  # dense, ragged tail
+    ([[0, 0, 0]] * 3 + [[1]], 5000),     # mixed
+])
+def test_event_overflow_and_dense_threshold(pats, n):
+    rng = W.rng_for(n)
+    text = np.zeros(n, dtype=np.uint8)
+    text[rng.integers(0, n, n // 10)] = 1          # a few breaks in the runs
+    inst = W.Instance(text, W.PatternSet.from_list(pats), 4, W.DNA)
+    for fmt in (0, 1):
+        _parity(inst, fmt, tune={"chunk": 128})
