@@ -109,10 +109,11 @@ typedef struct {
 
 /* Launch shape of a scan.  Zero fields take the library's choice. */
 typedef struct {
-    uint32_t chunk;         /* text symbols owned by one lane, multiple of 64 */
+    uint32_t chunk;         /* text symbols per chunk: multiple of 64, <= 2048 */
     uint32_t block_threads; /* 64..1024, multiple of 64                      */
     uint32_t placement;     /* AC_PLACE_*; AUTO = the dictionary's default   */
     uint32_t blocks_per_cu; /* persistent blocks per compute unit            */
+    uint32_t chains;        /* chunks walked at once by one lane: 1, 2 or 4  */
 } ac_tune;
 
 /* ---------------------------------------------------------------- stage 1

@@ -89,7 +89,8 @@ class ac_dict_info(ctypes.Structure):
 
 class ac_tune(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_uint32), ("block_threads", ctypes.c_uint32),
-                ("placement", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32)]
+                ("placement", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
+                ("chains", ctypes.c_uint32)]
 
 
 class ac_batch_item(ctypes.Structure):
@@ -175,7 +176,7 @@ def _tune(t) -> Optional[ac_tune]:
     if isinstance(t, ac_tune):
         return t
     return ac_tune(t.get("chunk", 0), t.get("block_threads", 0), t.get("placement", 0),
-                   t.get("blocks_per_cu", 0))
+                   t.get("blocks_per_cu", 0), t.get("chains", 0))
 
 
 def _tune_ref(t):

@@ -88,61 +88,115 @@ struct ChunkOut {
     uint32_t dense;  // of which with >= kDenseMatches matches
 };
 
-template <int FMT, int PLACE>
-__device__ __forceinline__ ChunkOut walk_count(const UTable<PLACE> &tab, const UText &txt,
-                                               const uint32_t *__restrict__ out_off, uint32_t fo,
-                                               uint32_t fo_state, uint32_t tz, uint32_t inv,
-                                               uint32_t j, uint32_t chunk, uint32_t warm,
-                                               uint32_t lim, uint32_t *__restrict__ seg_state,
-                                               uint32_t *__restrict__ seg_m, uint32_t seg0) {
+// Per-lane geometry of one chain (one chunk).
+struct ChainIn {
+    uint32_t j;     // chunk (instance-local)
+    uint32_t lim;   // symbols of the chunk inside the text (0: no chunk)
+    uint32_t seg0;  // first segment in the segment arrays
+};
+
+// Walk CH chunks at once (independent lookup chains that keep more loads in
+// flight per lane) and count the matches ending in each 64-symbol segment.
+// A word is walked with one lookup per symbol plus a running max; only a
+// word that reaches an output state adds output-set sizes (rare).  For each
+// segment with matches the entry state and the count are stored.
+template <int FMT, int PLACE, int CH>
+__device__ __forceinline__ void walk_count(const UTable<PLACE> &tab, const UText &txt,
+                                           const uint32_t *__restrict__ out_off, uint32_t fo,
+                                           uint32_t fo_state, uint32_t tz, uint32_t inv,
+                                           uint32_t chunk, uint32_t warm, const ChainIn (&in)[CH],
+                                           uint32_t *__restrict__ seg_state,
+                                           uint32_t *__restrict__ seg_m, ChunkOut (&r)[CH]) {
     constexpr uint32_t SPW = Fmt<FMT>::SPW;
     constexpr uint32_t WPS = kSeg / SPW;  // text words per segment
     const uint32_t wpc = chunk / SPW, spc = chunk / kSeg;
-    const uint32_t w0 = j * wpc;
-    uint32_t s = warm_up<FMT>(tab, txt, (int)w0, warm);
-    ChunkOut r = {0, 0, 0};
-    u32x4 nx = txt.vec(w0);
+    uint32_t s[CH], w0[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+        w0[c] = in[c].j * wpc;
+        s[c] = 0;
+        r[c] = ChunkOut{0, 0, 0};
+    }
+    // warm-up, chains interleaved
+    for (uint32_t i = 0; i < warm; ++i) {
+        uint32_t x[CH];
+        bool live[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int w = (int)w0[c] - (int)warm + (int)i;
+            x[c] = txt.word(w);
+            live[c] = w >= 0;
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < SPW; ++k) {
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const uint32_t ns = tab(s[c] + sym_bytes<FMT>(x[c], k));
+                s[c] = live[c] ? ns : s[c];
+            }
+        }
+    }
+    u32x4 nx[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) nx[c] = txt.vec(w0[c]);
     for (uint32_t g = 0; g < spc; ++g) {
-        const uint32_t s_entry = s;
-        uint32_t sm = 0;
+        uint32_t s_entry[CH], sm[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            s_entry[c] = s[c];
+            sm[c] = 0;
+        }
 #pragma unroll
         for (uint32_t v = 0; v < WPS; v += 4) {
-            const u32x4 x4 = nx;
+            u32x4 x4[CH];
             const uint32_t wn = g * WPS + v + 4;
-            if (wn < wpc) nx = txt.vec(w0 + wn);
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                x4[c] = nx[c];
+                if (wn < wpc) nx[c] = txt.vec(w0[c] + wn);
+            }
 #pragma unroll
             for (uint32_t q = 0; q < 4; ++q) {
-                const uint32_t x = x4[q];
-                uint32_t st[SPW];
-                uint32_t acc = 0;
+                uint32_t st[CH][SPW];
+                uint32_t acc[CH];
+#pragma unroll
+                for (int c = 0; c < CH; ++c) acc[c] = 0;
 #pragma unroll
                 for (uint32_t k = 0; k < SPW; ++k) {
-                    s = tab(s + sym_bytes<FMT>(x, k));
-                    st[k] = s;
-                    acc = acc > s ? acc : s;
-                }
-                if (acc >= fo) {
-                    // some state of this word has an output set: add sizes
-                    const uint32_t p0 = (g * WPS + v + q) * SPW;
 #pragma unroll
-                    for (uint32_t k = 0; k < SPW; ++k) {
-                        if (st[k] >= fo && p0 + k < lim) {
-                            const uint32_t o = row_state(st[k], tz, inv) - fo_state;
-                            sm += out_off[o + 1] - out_off[o];
+                    for (int c = 0; c < CH; ++c) {
+                        s[c] = tab(s[c] + sym_bytes<FMT>(x4[c][q], k));
+                        st[c][k] = s[c];
+                        acc[c] = acc[c] > s[c] ? acc[c] : s[c];
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    if (acc[c] >= fo) {
+                        // some state of this word has an output set: add sizes
+                        const uint32_t p0 = (g * WPS + v + q) * SPW;
+#pragma unroll
+                        for (uint32_t k = 0; k < SPW; ++k) {
+                            if (st[c][k] >= fo && p0 + k < in[c].lim) {
+                                const uint32_t o = row_state(st[c][k], tz, inv) - fo_state;
+                                sm[c] += out_off[o + 1] - out_off[o];
+                            }
                         }
                     }
                 }
             }
         }
-        if (sm) {
-            r.mask |= 1u << g;
-            seg_state[seg0 + g] = s_entry;
-            seg_m[seg0 + g] = sm;
-            r.dense += sm >= kDenseMatches;
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            if (sm[c]) {
+                r[c].mask |= 1u << g;
+                seg_state[in[c].seg0 + g] = s_entry[c];
+                seg_m[in[c].seg0 + g] = sm[c];
+                r[c].dense += sm[c] >= kDenseMatches;
+            }
+            r[c].m += sm[c];
         }
-        r.m += sm;
     }
-    return r;
 }
 
 // Copy the LDS part of a table (zero-filled past the table's end).
@@ -153,8 +207,9 @@ __device__ __forceinline__ void load_lds_table(rsrc_t g, uint32_t bytes) {
 }
 
 // Persistent count kernel.  Block b takes a contiguous range of tiles; a
-// tile is blockDim.x chunks of one instance, one chunk per lane.
-template <int FMT, bool BATCH>
+// tile is CH * blockDim.x consecutive chunks of one instance: lane t walks
+// chunks first + t * CH + c for c < CH.
+template <int FMT, bool BATCH, int CH>
 __global__ __launch_bounds__(kMaxCountThreads) void k_count(
     Inst single, const Inst *__restrict__ insts, const TileDesc *__restrict__ tiles,
     uint32_t n_tiles, uint32_t chunk, uint32_t warm, uint32_t *__restrict__ cnt,
@@ -175,8 +230,8 @@ __global__ __launch_bounds__(kMaxCountThreads) void k_count(
             first = uniform(td.first);
             count = uniform(td.count);
         } else {
-            first = t * blockDim.x;
-            count = min(blockDim.x, single.n_chunks - first);
+            first = t * blockDim.x * CH;
+            count = min(blockDim.x * CH, single.n_chunks - first);
         }
         const Inst &I = BATCH ? insts[inst] : single;
         const uint32_t table_bytes = uniform(I.table_bytes);
@@ -198,31 +253,42 @@ __global__ __launch_bounds__(kMaxCountThreads) void k_count(
         const uint32_t fo = uniform(I.fo_bytes), fos = uniform(I.fo_state);
         const uint32_t tz = uniform(I.div_tz), inv = uniform(I.div_inv);
         const uint32_t cbase = uniform(I.chunk_base);
-        const uint32_t lane_chunk = first + threadIdx.x;
-        const bool valid = threadIdx.x < count;
-        const uint32_t j = valid ? lane_chunk : first;
-        const uint64_t begin = (uint64_t)j * chunk;
-        const uint32_t lim = valid ? (uint32_t)min<uint64_t>(chunk, n - begin) : 0u;
-        const uint32_t seg0 = (cbase + j) * spc;
-        ChunkOut c;
-        if (lds_all) {
-            c = walk_count<FMT, PL_LDS>(UTable<PL_LDS>{gtab, hot}, txt, out_off, fo, fos, tz, inv,
-                                        j, chunk, warm, lim, seg_state, seg_m, seg0);
-        } else if (hot == 0) {
-            c = walk_count<FMT, PL_GLOBAL>(UTable<PL_GLOBAL>{gtab, 0}, txt, out_off, fo, fos, tz,
-                                           inv, j, chunk, warm, lim, seg_state, seg_m, seg0);
-        } else {
-            c = walk_count<FMT, PL_HYBRID>(UTable<PL_HYBRID>{gtab, hot}, txt, out_off, fo, fos, tz,
-                                           inv, j, chunk, warm, lim, seg_state, seg_m, seg0);
+        ChainIn in[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const uint32_t k = threadIdx.x * CH + c;
+            const bool valid = k < count;
+            in[c].j = valid ? first + k : first;
+            const uint64_t begin = (uint64_t)in[c].j * chunk;
+            in[c].lim = valid ? (uint32_t)min<uint64_t>(chunk, n - begin) : 0u;
+            in[c].seg0 = (cbase + in[c].j) * spc;
         }
-        if (valid) {
-            cnt[cbase + lane_chunk] = c.m;
-            mask[cbase + lane_chunk] = c.mask;
+        ChunkOut co[CH];
+        if (lds_all) {
+            walk_count<FMT, PL_LDS, CH>(UTable<PL_LDS>{gtab, hot}, txt, out_off, fo, fos, tz, inv,
+                                        chunk, warm, in, seg_state, seg_m, co);
+        } else if (hot == 0) {
+            walk_count<FMT, PL_GLOBAL, CH>(UTable<PL_GLOBAL>{gtab, 0}, txt, out_off, fo, fos, tz,
+                                           inv, chunk, warm, in, seg_state, seg_m, co);
+        } else {
+            walk_count<FMT, PL_HYBRID, CH>(UTable<PL_HYBRID>{gtab, hot}, txt, out_off, fo, fos,
+                                           tz, inv, chunk, warm, in, seg_state, seg_m, co);
+        }
+        unsigned long long m = 0;
+        uint32_t zs = 0, zd = 0;
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            if (threadIdx.x * CH + c < count) {
+                cnt[cbase + in[c].j] = co[c].m;
+                mask[cbase + in[c].j] = co[c].mask;
+            }
+            m += co[c].m;
+            zs += __builtin_popcount(co[c].mask) - co[c].dense;
+            zd += co[c].dense;
         }
         // tile totals: matches, sparse and dense segments
-        const uint32_t nz = __builtin_popcount(c.mask);
-        const unsigned long long wa = wave_sum_u64(c.m);
-        const uint32_t wb = wave_sum_u32(nz - c.dense), wc = wave_sum_u32(c.dense);
+        const unsigned long long wa = wave_sum_u64(m);
+        const uint32_t wb = wave_sum_u32(zs), wc = wave_sum_u32(zd);
         const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
         if (lane == 0) {
             red_a[wid] = wa;
@@ -288,16 +354,18 @@ __global__ __launch_bounds__(1024) void k_tile_scan(
 // One block per tile: append every segment with matches to the work list,
 // with its entry state and the offset of its first match (relative to its
 // instance's output).  Sparse segments fill the list from the front in text
-// order, dense ones follow all sparse ones, also in text order.
+// order, dense ones follow all sparse ones, also in text order.  Thread t
+// handles the tile's chunks t * per .. t * per + per - 1.
 template <bool BATCH>
 __global__ __launch_bounds__(kMaxCountThreads) void k_scatter(
     Inst single, const Inst *__restrict__ insts, const TileDesc *__restrict__ tiles,
-    uint32_t chunk, const uint32_t *__restrict__ cnt, const uint32_t *__restrict__ mask,
-    const uint32_t *__restrict__ seg_state, const uint32_t *__restrict__ seg_m,
-    const unsigned long long *__restrict__ tile_moff, const uint32_t *__restrict__ tile_zsoff,
-    const uint32_t *__restrict__ tile_zdoff, const unsigned long long *__restrict__ totals,
-    uint32_t *__restrict__ list_seg, uint32_t *__restrict__ list_state,
-    unsigned long long *__restrict__ list_moff, uint32_t *__restrict__ list_inst) {
+    uint32_t chunk, uint32_t per, const uint32_t *__restrict__ cnt,
+    const uint32_t *__restrict__ mask, const uint32_t *__restrict__ seg_state,
+    const uint32_t *__restrict__ seg_m, const unsigned long long *__restrict__ tile_moff,
+    const uint32_t *__restrict__ tile_zsoff, const uint32_t *__restrict__ tile_zdoff,
+    const unsigned long long *__restrict__ totals, uint32_t *__restrict__ list_seg,
+    uint32_t *__restrict__ list_state, unsigned long long *__restrict__ list_moff,
+    uint32_t *__restrict__ list_inst) {
     const uint32_t t = blockIdx.x;
     const uint32_t spc = chunk / kSeg;
     uint32_t inst = 0, first, count, cbase = 0;
@@ -310,34 +378,42 @@ __global__ __launch_bounds__(kMaxCountThreads) void k_scatter(
         cbase = insts[inst].chunk_base;
         base_off = tile_moff[insts[inst].first_tile];
     } else {
-        first = t * blockDim.x;
-        count = min(blockDim.x, single.n_chunks - first);
+        first = t * blockDim.x * per;
+        count = min(blockDim.x * per, single.n_chunks - first);
     }
-    const bool valid = threadIdx.x < count;
-    const uint32_t j = first + threadIdx.x;
-    const uint32_t g = cbase + j;
-    const uint32_t m = valid ? cnt[g] : 0u;
-    const uint32_t mk = valid ? mask[g] : 0u;
-    uint32_t zd = 0;
-    for (uint32_t b = mk; b; b &= b - 1)
-        zd += seg_m[g * spc + __builtin_ctz(b)] >= kDenseMatches;
-    const uint32_t zs = __builtin_popcount(mk) - zd;
+    const uint32_t k0 = threadIdx.x * per;
+    const uint32_t k1 = min(k0 + per, count);
+    unsigned long long m = 0;
+    uint32_t zs = 0, zd = 0;
+    for (uint32_t k = k0; k < k1; ++k) {
+        const uint32_t g = cbase + first + k;
+        m += cnt[g];
+        const uint32_t mk = mask[g];
+        uint32_t d = 0;
+        for (uint32_t b = mk; b; b &= b - 1) d += seg_m[g * spc + __builtin_ctz(b)] >= kDenseMatches;
+        zd += d;
+        zs += __builtin_popcount(mk) - d;
+    }
     Scan3 ex, tot;
     block_excl_scan3(Scan3{m, zs, zd}, &ex, &tot);
     const uint32_t n_sparse = (uint32_t)totals[1];
     uint32_t ks = tile_zsoff[t] + ex.b;
     uint32_t kd = n_sparse + tile_zdoff[t] + ex.c;
     unsigned long long off = tile_moff[t] + ex.a - base_off;
-    for (uint32_t b = mk; b; b &= b - 1) {
-        const uint32_t i = __builtin_ctz(b);
-        const uint32_t gs = g * spc + i;
-        const uint32_t sm = seg_m[gs];
-        const uint32_t k = sm >= kDenseMatches ? kd++ : ks++;
-        list_seg[k] = j * spc + i;
-        list_state[k] = seg_state[gs];
-        list_moff[k] = off;
-        if constexpr (BATCH) list_inst[k] = inst;
-        off += sm;
+    for (uint32_t k = k0; k < k1; ++k) {
+        const uint32_t j = first + k;
+        const uint32_t g = cbase + j;
+        for (uint32_t b = mask[g]; b; b &= b - 1) {
+            const uint32_t i = __builtin_ctz(b);
+            const uint32_t gs = g * spc + i;
+            const uint32_t sm = seg_m[gs];
+            const uint32_t kk = sm >= kDenseMatches ? kd++ : ks++;
+            list_seg[kk] = j * spc + i;
+            list_state[kk] = seg_state[gs];
+            list_moff[kk] = off;
+            if constexpr (BATCH) list_inst[kk] = inst;
+            off += sm;
+        }
     }
 }
 
@@ -489,16 +565,25 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
 }
 
 // Dense part of the work list: one wave per listed segment.  The wave walks
-// the segment once (all lanes together, so every lookup is one broadcast
-// read); lane k keeps the state entered at position k.  A prefix sum of the
-// output-set sizes over the wave gives each position its first slot.  The
-// positions are then written one after the other, each by the whole wave:
-// lane i writes match i of the set, so every store instruction covers 64
-// consecutive 8-byte slots.  The ids of the last set written stay in
-// registers, so a run of positions in the same state (a poly-A run, say)
-// loads them once.
+// the segment once (all lanes together, so each lookup is one broadcast
+// read); lane k keeps the state entered at position k and, before any store
+// is issued, loads where that state's output set starts and how long it is.
+// A prefix sum over the wave gives every position its first slot.
+//
+// The positions are then written as runs of equal states (a poly-A run is
+// one long run of the deepest all-A state): a run of r positions whose set
+// has L ids is r * L consecutive slots, item t of the run being id t % L at
+// end position first + t / L.  The wave writes the run item-parallel, lane i
+// taking items i, i + 64, ... (with a trip count uniform over the wave, so
+// no lane is inactive during a shuffle), so every store instruction covers 64
+// consecutive 8-byte slots; the run's ids sit in two registers per lane and
+// are picked with a wave shuffle (an LDS-path operation, which does not wait
+// for the wave's stores the way a memory load would).  Sets longer than 128
+// ids take a slower path that loads them per position.
+constexpr uint32_t kDenseThreads = 256;
+
 template <int FMT, bool BATCH>
-__global__ __launch_bounds__(kEmitThreads) void k_emit_dense(
+__global__ __launch_bounds__(kDenseThreads) void k_emit_dense(
     Inst single, const Inst *__restrict__ insts, const uint32_t *__restrict__ list_seg,
     const uint32_t *__restrict__ list_state, const unsigned long long *__restrict__ list_moff,
     const uint32_t *__restrict__ list_inst, const unsigned long long *__restrict__ totals) {
@@ -525,6 +610,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_dense(
         const uint32_t *ids = uniform(I.out_ids);
         ac_match *out = uniform(I.out);
         const unsigned long long cap = uniform(I.capacity);
+        if (off0 >= cap) continue;
         const UTable<PL_GLOBAL> tab{make_rsrc(uniform(I.delta), tb), 0};
         const UText txt{make_rsrc(uniform(I.text), tb4), tb4};
         uint32_t mine = 0;
@@ -540,47 +626,67 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_dense(
                 }
             }
         }
+        const bool has = mine >= fo && lane < lim;
         uint32_t a = 0, len = 0;
-        if (mine >= fo && lane < lim) {
+        if (has) {
             const uint32_t o = row_state(mine, tz, inv) - fos;
             a = out_off[o];
             len = out_off[o + 1] - a;
         }
         const uint32_t excl = wave_incl_scan(len) - len;
-        uint64_t todo = __ballot(len != 0);
-        uint32_t cur = 0xFFFFFFFFu, v0 = 0, v1 = 0;
-        while (todo) {
-            const uint32_t k = (uint32_t)__builtin_ctzll(todo);
-            todo &= todo - 1;
+        // runs: a run starts at an output position whose predecessor is in a
+        // different state or has no output; it ends before the next start or
+        // the next position without output
+        const uint32_t prev = __shfl_up(mine, 1, 64);
+        const bool prev_has = __shfl_up((uint32_t)has, 1, 64) != 0;
+        const bool start = has && (lane == 0 || !prev_has || prev != mine);
+        uint64_t starts = __ballot(start);
+        const uint64_t stops = __ballot(start || !has);
+        while (starts) {
+            const uint32_t k = (uint32_t)__builtin_ctzll(starts);
+            starts &= starts - 1;
+            const uint64_t after = stops & ~((2ull << k) - 1ull);  // bits above k
+            const uint32_t kend = after ? (uint32_t)__builtin_ctzll(after) : 64u;
+            const uint32_t r = kend - k;
+            const uint32_t L = __builtin_amdgcn_readlane(len, k);
             const uint32_t ka = __builtin_amdgcn_readlane(a, k);
-            const uint32_t kl = __builtin_amdgcn_readlane(len, k);
             const unsigned long long ko = off0 + __builtin_amdgcn_readlane(excl, k);
             if (ko >= cap) break;
+            const uint32_t T = r * L;
             const uint32_t e = e0 + k;
-            if (kl <= 128) {
-                if (ka != cur) {
-                    v0 = lane < kl ? ids[ka + lane] : 0u;
-                    v1 = lane + 64 < kl ? ids[ka + 64 + lane] : 0u;
-                    cur = ka;
-                }
-                if (lane < kl && ko + lane < cap) {
-                    ac_match m;
-                    m.pattern_id = v0;
-                    m.end_pos = e;
-                    out[ko + lane] = m;
-                }
-                if (lane + 64 < kl && ko + 64 + lane < cap) {
-                    ac_match m;
-                    m.pattern_id = v1;
-                    m.end_pos = e;
-                    out[ko + 64 + lane] = m;
+            if (L <= 128) {
+                const uint32_t v0 = lane < L ? ids[ka + lane] : 0u;
+                const uint32_t v1 = lane + 64 < L ? ids[ka + 64 + lane] : 0u;
+                const float rcp = 1.0f / (float)L;
+                const bool all_in = ko + T <= cap;
+                // uniform trip count: every lane takes part in each shuffle
+#pragma unroll 2
+                for (uint32_t base = 0; base < T; base += 64) {
+                    const uint32_t t = base + lane;
+                    uint32_t i = (uint32_t)((float)t * rcp);
+                    if (i * L > t) --i;
+                    else if ((i + 1) * L <= t) ++i;
+                    const uint32_t j = t - i * L;
+                    const uint32_t x0 = (uint32_t)__shfl(v0, j & 63, 64);
+                    const uint32_t x1 = (uint32_t)__shfl(v1, j & 63, 64);
+                    if (t < T && (all_in || ko + t < cap)) {
+                        ac_match m;
+                        m.pattern_id = j < 64 ? x0 : x1;
+                        m.end_pos = e + i;
+                        out[ko + t] = m;
+                    }
                 }
             } else {
-                for (uint32_t i = lane; i < kl && ko + i < cap; i += 64) {
-                    ac_match m;
-                    m.pattern_id = ids[ka + i];
-                    m.end_pos = e;
-                    out[ko + i] = m;
+                for (uint32_t i = 0; i < r; ++i) {
+                    for (uint32_t j = lane; j < L; j += 64) {
+                        const unsigned long long d = ko + (unsigned long long)i * L + j;
+                        if (d < cap) {
+                            ac_match m;
+                            m.pattern_id = ids[ka + j];
+                            m.end_pos = e + i;
+                            out[d] = m;
+                        }
+                    }
                 }
             }
         }
@@ -804,7 +910,7 @@ static uint32_t spw_of(uint32_t fmt) { return fmt == AC_TEXT_2BIT ? 16u : 4u; }
 static uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
 struct Geom {
-    uint32_t chunk = 0, threads = 0, warm = 0, grid_count = 0;
+    uint32_t chunk = 0, threads = 0, warm = 0, grid_count = 0, chains = 1;
     uint32_t grid_emit = 0, grid_dense = 0;  // bounded by the largest possible work list
     uint32_t lds_bytes = 0;  // dynamic LDS of k_count
     uint64_t n_chunks = 0, n_tiles = 0;
@@ -896,6 +1002,9 @@ static int resolve_geom(const ac_dict *const *dicts, const uint64_t *ns, uint32_
     g->warm = (max_len - 1 + spw - 1) / spw;
     g->threads = (tune && tune->block_threads) ? tune->block_threads : 1024u;
     if (g->threads < 64 || g->threads > kMaxCountThreads || g->threads % 64) return AC_E_INVALID;
+    g->chains = (tune && tune->chains) ? tune->chains : 2u;
+    if (g->chains != 1 && g->chains != 2 && g->chains != 4) return AC_E_INVALID;
+    const uint32_t per_tile = g->threads * g->chains;  // chunks per tile
     uint32_t chunk = tune ? tune->chunk : 0;
     if (chunk && (chunk % kSeg || chunk > kMaxChunk)) return AC_E_INVALID;
     if (chunk > max_chunk) return AC_E_TOO_LARGE;
@@ -915,7 +1024,7 @@ static int resolve_geom(const ac_dict *const *dicts, const uint64_t *ns, uint32_
     const uint64_t slots = (uint64_t)cus * bpc;
     if (!chunk) {
         chunk = std::min<uint32_t>(1024, max_chunk);
-        while (chunk > kSeg && (total / chunk) / g->threads < slots) chunk /= 2;
+        while (chunk > kSeg && (total / chunk) / per_tile < slots) chunk /= 2;
     }
     g->chunk = chunk;
     g->n_chunks = 0;
@@ -923,7 +1032,7 @@ static int resolve_geom(const ac_dict *const *dicts, const uint64_t *ns, uint32_
     for (uint32_t i = 0; i < n_inst; ++i) {
         const uint64_t c = (ns[i] + chunk - 1) / chunk;
         g->n_chunks += c;
-        g->n_tiles += (c + g->threads - 1) / g->threads;
+        g->n_tiles += (c + per_tile - 1) / per_tile;
     }
     if (g->n_chunks >= (1ull << 31) || g->n_tiles >= (1ull << 31)) return AC_E_TOO_LARGE;
     g->grid_count = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g->n_tiles, slots));
@@ -932,7 +1041,7 @@ static int resolve_geom(const ac_dict *const *dicts, const uint64_t *ns, uint32_
     g->grid_emit = (uint32_t)std::max<uint64_t>(
         1, std::min<uint64_t>((uint64_t)cus * 8, (segs + kEmitThreads - 1) / kEmitThreads));
     g->grid_dense = (uint32_t)std::max<uint64_t>(
-        1, std::min<uint64_t>((uint64_t)cus * 8, (segs + kEmitThreads / 64 - 1) / (kEmitThreads / 64)));
+        1, std::min<uint64_t>((uint64_t)cus * 8, (segs + kDenseThreads / 64 - 1) / (kDenseThreads / 64)));
     return AC_OK;
 }
 
@@ -978,18 +1087,34 @@ static int validate_text(const ac_dict *d, const void *text, uint64_t n, uint32_
     return AC_OK;
 }
 
+template <int FMT, bool BATCH, int CH>
+static int launch_count_ch(const Geom &g, const Inst &I, const Inst *insts,
+                           const TileDesc *tiles, const Workspace &w, hipStream_t st) {
+    auto kc = k_count<FMT, BATCH, CH>;
+    int rc = allow_lds(kc, g.lds_bytes);
+    if (rc) return rc;
+    KTimer tm(AC_K_COUNT, st);
+    hipLaunchKernelGGL(kc, dim3(g.grid_count), dim3(g.threads), g.lds_bytes, st, I, insts, tiles,
+                       (uint32_t)g.n_tiles, g.chunk, g.warm, w.cnt, w.mask, w.seg_state, w.seg_m,
+                       w.tile_m, w.tile_zs, w.tile_zd);
+    return AC_OK;
+}
+
+template <int FMT, bool BATCH>
+static int launch_count(const Geom &g, const Inst &I, const Inst *insts, const TileDesc *tiles,
+                        const Workspace &w, hipStream_t st) {
+    switch (g.chains) {
+        case 1: return launch_count_ch<FMT, BATCH, 1>(g, I, insts, tiles, w, st);
+        case 2: return launch_count_ch<FMT, BATCH, 2>(g, I, insts, tiles, w, st);
+        default: return launch_count_ch<FMT, BATCH, 4>(g, I, insts, tiles, w, st);
+    }
+}
+
 template <int FMT>
 static int launch_single(const Geom &g, const Inst &I, const Workspace &w, hipStream_t st) {
     const uint32_t T = (uint32_t)g.n_tiles;
-    auto kc = k_count<FMT, false>;
-    int rc = allow_lds(kc, g.lds_bytes);
+    int rc = launch_count<FMT, false>(g, I, nullptr, nullptr, w, st);
     if (rc) return rc;
-    {
-        KTimer tm(AC_K_COUNT, st);
-        hipLaunchKernelGGL(kc, dim3(g.grid_count), dim3(g.threads), g.lds_bytes, st, I, nullptr,
-                           nullptr, T, g.chunk, g.warm, w.cnt, w.mask, w.seg_state, w.seg_m,
-                           w.tile_m, w.tile_zs, w.tile_zd);
-    }
     {
         KTimer tm(AC_K_OFFSETS, st);
         hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, w.tile_m, w.tile_zs,
@@ -999,7 +1124,7 @@ static int launch_single(const Geom &g, const Inst &I, const Workspace &w, hipSt
     {
         KTimer tm(AC_K_SCATTER, st);
         hipLaunchKernelGGL(k_scatter<false>, dim3(T), dim3(g.threads), 0, st, I, nullptr, nullptr,
-                           g.chunk, w.cnt, w.mask, w.seg_state, w.seg_m, w.tile_moff,
+                           g.chunk, g.chains, w.cnt, w.mask, w.seg_state, w.seg_m, w.tile_moff,
                            w.tile_zsoff, w.tile_zdoff, w.totals, w.list_seg, w.list_state,
                            w.list_moff, nullptr);
     }
@@ -1010,7 +1135,7 @@ static int launch_single(const Geom &g, const Inst &I, const Workspace &w, hipSt
     }
     {
         KTimer tm(AC_K_EMIT_DENSE, st);
-        hipLaunchKernelGGL((k_emit_dense<FMT, false>), dim3(g.grid_dense), dim3(kEmitThreads), 0,
+        hipLaunchKernelGGL((k_emit_dense<FMT, false>), dim3(g.grid_dense), dim3(kDenseThreads), 0,
                            st, I, nullptr, w.list_seg, w.list_state, w.list_moff, nullptr,
                            w.totals);
     }

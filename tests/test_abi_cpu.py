@@ -142,5 +142,5 @@ def test_info_struct_layout():
     # header's field lists)
     assert ctypes.sizeof(ac.ac_match) == 8
     assert ctypes.sizeof(ac.ac_build_opts) == 16
-    assert ctypes.sizeof(ac.ac_tune) == 16
+    assert ctypes.sizeof(ac.ac_tune) == 20
     assert ctypes.sizeof(ac.ac_batch_item) == 56

@@ -263,3 +263,31 @@ def test_event_overflow_and_dense_threshold(pats, n):
     inst = W.Instance(text, W.PatternSet.from_list(pats), 4, W.DNA)
     for fmt in (0, 1):
         _parity(inst, fmt, tune={"chunk": 128})
+
+
+@pytest.mark.parametrize("chains", [1, 2, 4])
+def test_chains_per_lane(chains):
+    for inst, fmt in ((W.dna_dense(scale=1 / 512), ac.AC_TEXT_2BIT),
+                      (W.protein(scale=1 / 256), ac.AC_TEXT_U8),
+                      (W.dna_small(scale=1 / 8), ac.AC_TEXT_U8)):
+        for place in (ac.AC_PLACE_AUTO, ac.AC_PLACE_GLOBAL):
+            _parity(inst, fmt, tune={"chains": chains, "placement": place, "chunk": 128,
+                                     "block_threads": 256})
+
+
+def test_output_buffer_not_16_byte_aligned():
+    # the dense writer pairs slots into 16-byte stores by address; start the
+    # output one slot (8 bytes) into a buffer
+    torch = torch_cuda()
+    inst = W.dna_dense(scale=1 / 256)
+    d = ac.ac_build(inst.patterns, sigma=4)
+    t = device_text(inst, ac.AC_TEXT_2BIT)
+    want = oracle.Machine(inst.patterns, 4).scan_keys(inst.text)
+    buf = torch.full((len(want) + 3, 2), -1, dtype=torch.int32, device="cuda")
+    out = buf[1:]
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ac.ac_scan(d, t, len(inst.text), ac.AC_TEXT_2BIT, out, len(want), cnt)
+    torch.cuda.synchronize()
+    assert int(cnt.item()) == len(want)
+    assert np.array_equal(ac.match_keys(out[:len(want)]), want)
+    assert (buf[0] == -1).all() and (buf[len(want) + 1:] == -1).all()
