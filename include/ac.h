@@ -66,7 +66,7 @@ extern "C" {
 #define AC_PLACE_AUTO 0     /* library chooses                              */
 #define AC_PLACE_LDS 1      /* whole table in LDS (must fit)                */
 #define AC_PLACE_GLOBAL 2   /* table read through L1/L2 from HBM            */
-#define AC_PLACE_HYBRID 3   /* first hot_states rows in LDS, rest global    */
+#define AC_PLACE_HYBRID 3   /* most visited rows in LDS as 16-bit ids, rest global */
 
 #define AC_BUILD_HOST_ONLY 1u /* compile tables on the host only (no GPU)   */
 
@@ -100,7 +100,7 @@ typedef struct {
     uint32_t first_output_state; /* states >= this have a non-empty output */
     uint32_t max_output;         /* largest output set                     */
     uint32_t placement;          /* default placement chosen by ac_build   */
-    uint32_t hot_states;         /* rows in LDS for AC_PLACE_HYBRID        */
+    uint32_t hot_states;         /* rows in LDS (16-bit) for AC_PLACE_HYBRID */
     uint32_t has_device;         /* 1 if the GPU tables exist              */
     uint64_t output_entries;     /* sum of output-set sizes                */
     uint64_t table_bytes;        /* dense table, bytes                     */

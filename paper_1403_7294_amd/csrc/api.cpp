@@ -2,6 +2,7 @@
 // releasing dictionaries.  The scan entry points live in scan.hip.
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <new>
 
@@ -63,7 +64,7 @@ int ac_dict_get_info(const ac_dict *d, ac_dict_info *info) {
     info->first_output_state = T.first_output;
     info->max_output = T.max_output;
     info->placement = d->placement;
-    info->hot_states = d->hot_states;
+    info->hot_states = d->hot_states ? std::min(d->hot_states, d->hot16_rows) : d->hot16_rows;
     info->has_device = d->d_delta != nullptr;
     info->output_entries = T.out_ids.size();
     info->table_bytes = d->table_bytes;

@@ -13,12 +13,17 @@
 //     loop ("read the same input character again") amounts to.  Rows are
 //     filled in breadth-first order, so delta(f(s), .) is complete before s.
 //  4. output sets: out(s) = keywords ending at s plus out(f(s)), ids sorted.
-//  5. renumbering: root 0, then output-free states, then output states, each
-//     group in breadth-first order.
+//  5. renumbering: root 0, then output-free states from most to least
+//     likely to be visited, then output states in breadth-first order.  The
+//     visit likelihood of a state is estimated as the probability of its
+//     string under independent symbols with the frequencies of the pattern
+//     symbols (the shallow, common prefixes first); the scan keeps the first
+//     rows of the table in LDS.
 #include <stdint.h>
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <vector>
 
 #include "internal.h"
@@ -114,8 +119,6 @@ int compile_automaton(const uint8_t *symbols, const uint64_t *offsets, uint32_t 
             }
         }
     }
-    child.clear();
-    child.shrink_to_fit();
 
     // ---- 4. output sets, in breadth-first order (f(s) before s)
     std::vector<uint32_t> own_cnt(S + 1, 0);
@@ -152,10 +155,29 @@ int compile_automaton(const uint8_t *symbols, const uint64_t *offsets, uint32_t 
     }
 
     // ---- 5. renumbering
+    std::vector<double> logp_sym(sigma, 0.0);
+    {
+        std::vector<uint64_t> freq(sigma, 1);  // add-one smoothing
+        for (uint64_t k = 0; k < total; ++k) freq[symbols[k]]++;
+        const double all = (double)(total + sigma);
+        for (uint32_t a = 0; a < sigma; ++a) logp_sym[a] = std::log((double)freq[a] / all);
+    }
+    std::vector<double> logp(S, 0.0);
+    for (uint32_t s : bfs)
+        for (uint32_t a = 0; a < sigma; ++a) {
+            const int32_t t = child[(size_t)s * sigma + a];
+            if (t >= 0) logp[t] = logp[s] + logp_sym[a];
+        }
+    child.clear();
+    child.shrink_to_fit();
     std::vector<uint32_t> order;
     order.reserve(S);
     for (uint32_t s : bfs)
         if (set_len[s] == 0) order.push_back(s);
+    // root first (log-probability 0), then by decreasing probability; the
+    // stable sort keeps breadth-first order among equals
+    std::stable_sort(order.begin(), order.end(),
+                     [&](uint32_t x, uint32_t y) { return logp[x] > logp[y]; });
     const uint32_t first_output = (uint32_t)order.size();
     for (uint32_t s : bfs)
         if (set_len[s] != 0) order.push_back(s);

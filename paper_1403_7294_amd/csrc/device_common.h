@@ -130,22 +130,39 @@ __device__ __forceinline__ uint32_t sym_bytes(uint32_t x, uint32_t k) {
         return __builtin_amdgcn_ubfe(x, 8 * k, 8) << 2;
 }
 
-// Table of one wave-uniform dictionary.
+// Byte-addressed 16-bit read of the dynamic LDS region.
+__device__ __forceinline__ uint32_t lds_load_u16(uint32_t byte_addr) {
+    extern __shared__ uint32_t dyn_smem[];
+    typedef __attribute__((address_space(3))) uint16_t lds_u16;
+    return *(lds_u16 *)((lds_u8 *)(lds_u32 *)dyn_smem + byte_addr);
+}
+
+// Table of one wave-uniform dictionary.  Lookups take the byte address
+// a = row offset + 4 * symbol in the 32-bit table and return the next
+// state's row offset.
+//   PL_LDS     the whole 32-bit table is in LDS;
+//   PL_GLOBAL  the table is read through the L1/L2 caches;
+//   PL_HYBRID  rows below `hot` (a byte bound in the 32-bit table) are in
+//              LDS as 16-bit state ids, at half the byte address; an id of
+//              0xFFFF (a state too far down the numbering for 16 bits) and
+//              every other row are read from the 32-bit table.
 template <int PLACE>
 struct UTable {
     rsrc_t g;
-    uint32_t hot;  // bytes of the table held in LDS (hybrid)
+    uint32_t hot;  // hybrid: first row offset not held in LDS
+    uint32_t row;  // hybrid: sigma * 4, bytes of a 32-bit row
     __device__ __forceinline__ uint32_t operator()(uint32_t a) const {
         if constexpr (PLACE == PL_LDS) {
             return lds_load(a);
         } else if constexpr (PLACE == PL_GLOBAL) {
             return buf_load(g, a);
         } else {
-            uint32_t v;
-            if (a < hot)
-                v = lds_load(a);
-            else
-                v = buf_load(g, a);
+            uint32_t v = 0xFFFFFFFFu;
+            if (a < hot) {
+                const uint32_t h = lds_load_u16(a >> 1);
+                if (h != 0xFFFFu) v = h * row;
+            }
+            if (v == 0xFFFFFFFFu) v = buf_load(g, a);
             return v;
         }
     }
@@ -166,6 +183,20 @@ struct UText {
         v.y = buf_load(r, o + 4);
         v.z = buf_load(r, o + 8);
         v.w = buf_load(r, o + 12);
+        return v;
+    }
+    // Same, marked non-temporal: text read once should not push the
+    // transition table out of the L2 cache.
+    __device__ __forceinline__ u32x4 vec_once(uint32_t w) const {
+        constexpr int kNonTemporal = 2;  // cache-policy bit "nt" of gfx94x/gfx950
+        const uint32_t o = w * 4u;
+        if (o + 16u <= bytes4)
+            return __builtin_amdgcn_raw_buffer_load_b128(r, o, 0, kNonTemporal);
+        u32x4 v;
+        v.x = __builtin_amdgcn_raw_buffer_load_b32(r, o, 0, kNonTemporal);
+        v.y = __builtin_amdgcn_raw_buffer_load_b32(r, o + 4, 0, kNonTemporal);
+        v.z = __builtin_amdgcn_raw_buffer_load_b32(r, o + 8, 0, kNonTemporal);
+        v.w = __builtin_amdgcn_raw_buffer_load_b32(r, o + 12, 0, kNonTemporal);
         return v;
     }
 };

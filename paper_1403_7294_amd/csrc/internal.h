@@ -58,6 +58,8 @@ struct ac_dict {
     uint32_t *d_delta = nullptr;    // states*sigma row byte offsets
     uint32_t *d_out_off = nullptr;
     uint32_t *d_out_ids = nullptr;
+    uint16_t *d_hot16 = nullptr;  // first hot16_rows rows as 16-bit ids (0xFFFF: see table)
+    uint32_t hot16_rows = 0;
     uint64_t table_bytes = 0;
 };
 

@@ -54,6 +54,7 @@ struct Inst {
     const uint32_t *delta;  // row byte offsets: delta[s*sigma+a] = next*sigma*4
     const uint32_t *out_off;
     const uint32_t *out_ids;
+    const uint16_t *hot16;   // 16-bit rows for the hybrid placement
     const uint8_t *text;
     ac_match *out;
     unsigned long long *count;
@@ -63,8 +64,9 @@ struct Inst {
     uint32_t table_bytes;
     uint32_t fo_bytes;     // row offset of the first state with output
     uint32_t fo_state;     // its state number
-    uint32_t hot_bytes;    // table bytes kept in LDS (0, part, or all)
+    uint32_t hot_bytes;    // LDS: table bytes; hybrid: first row offset not in LDS; else 0
     uint32_t lds_all;      // 1: whole table in LDS (with zero pad)
+    uint32_t lds_bytes;    // bytes the count kernel copies into LDS
     uint32_t n_chunks;
     uint32_t chunk_base;   // first chunk of this instance in the chunk arrays
     uint32_t first_tile;   // first tile of this instance
@@ -138,7 +140,7 @@ __device__ __forceinline__ void walk_count(const UTable<PLACE> &tab, const UText
     }
     u32x4 nx[CH];
 #pragma unroll
-    for (int c = 0; c < CH; ++c) nx[c] = txt.vec(w0[c]);
+    for (int c = 0; c < CH; ++c) nx[c] = txt.vec_once(w0[c]);
     for (uint32_t g = 0; g < spc; ++g) {
         uint32_t s_entry[CH], sm[CH];
 #pragma unroll
@@ -153,7 +155,7 @@ __device__ __forceinline__ void walk_count(const UTable<PLACE> &tab, const UText
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
                 x4[c] = nx[c];
-                if (wn < wpc) nx[c] = txt.vec(w0[c] + wn);
+                if (wn < wpc) nx[c] = txt.vec_once(w0[c] + wn);
             }
 #pragma unroll
             for (uint32_t q = 0; q < 4; ++q) {
@@ -237,11 +239,16 @@ __global__ __launch_bounds__(kMaxCountThreads) void k_count(
         const uint32_t table_bytes = uniform(I.table_bytes);
         const uint32_t hot = uniform(I.hot_bytes);
         const uint32_t lds_all = uniform(I.lds_all);
+        const uint32_t row = uniform(I.sigma) * 4u;
         const rsrc_t gtab = make_rsrc(uniform(I.delta), table_bytes);
         if ((int)inst != cur) {
             if (hot) {
+                const uint32_t lb = uniform(I.lds_bytes);
                 __syncthreads();
-                load_lds_table(gtab, lds_all ? hot + kLdsPad : hot);
+                if (lds_all)
+                    load_lds_table(gtab, lb);
+                else
+                    load_lds_table(make_rsrc(uniform(I.hot16), lb), lb);
                 __syncthreads();
             }
             cur = (int)inst;
@@ -265,13 +272,13 @@ __global__ __launch_bounds__(kMaxCountThreads) void k_count(
         }
         ChunkOut co[CH];
         if (lds_all) {
-            walk_count<FMT, PL_LDS, CH>(UTable<PL_LDS>{gtab, hot}, txt, out_off, fo, fos, tz, inv,
+            walk_count<FMT, PL_LDS, CH>(UTable<PL_LDS>{gtab, hot, row}, txt, out_off, fo, fos, tz, inv,
                                         chunk, warm, in, seg_state, seg_m, co);
         } else if (hot == 0) {
-            walk_count<FMT, PL_GLOBAL, CH>(UTable<PL_GLOBAL>{gtab, 0}, txt, out_off, fo, fos, tz,
+            walk_count<FMT, PL_GLOBAL, CH>(UTable<PL_GLOBAL>{gtab, 0, row}, txt, out_off, fo, fos, tz,
                                            inv, chunk, warm, in, seg_state, seg_m, co);
         } else {
-            walk_count<FMT, PL_HYBRID, CH>(UTable<PL_HYBRID>{gtab, hot}, txt, out_off, fo, fos,
+            walk_count<FMT, PL_HYBRID, CH>(UTable<PL_HYBRID>{gtab, hot, row}, txt, out_off, fo, fos,
                                            tz, inv, chunk, warm, in, seg_state, seg_m, co);
         }
         unsigned long long m = 0;
@@ -558,7 +565,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
         if constexpr (BATCH) {
             body(LTable{I.delta, I.table_bytes}, LText{(const uint32_t *)I.text, I.text_bytes4});
         } else {
-            body(UTable<PL_GLOBAL>{make_rsrc(single.delta, single.table_bytes), 0},
+            body(UTable<PL_GLOBAL>{make_rsrc(single.delta, single.table_bytes), 0, 0},
                  UText{make_rsrc(single.text, single.text_bytes4), single.text_bytes4});
         }
     }
@@ -611,7 +618,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_emit_dense(
         ac_match *out = uniform(I.out);
         const unsigned long long cap = uniform(I.capacity);
         if (off0 >= cap) continue;
-        const UTable<PL_GLOBAL> tab{make_rsrc(uniform(I.delta), tb), 0};
+        const UTable<PL_GLOBAL> tab{make_rsrc(uniform(I.delta), tb), 0, 0};
         const UText txt{make_rsrc(uniform(I.text), tb4), tb4};
         uint32_t mine = 0;
 #pragma unroll
@@ -818,10 +825,25 @@ int device_limits(uint32_t *cus, uint32_t *lds) {
     return AC_OK;
 }
 
+// Largest dynamic LDS a count block may use (the kernel's static LDS is
+// below 512 bytes).
+static uint32_t count_lds_limit(uint32_t lds) { return lds - 512; }
+
 int upload_dict(ac_dict *d) {
     const HostTables &T = d->host;
     int dev = 0;
     HIP_OK(hipGetDevice(&dev));
+    uint32_t cus = 0, lds = 0;
+    int rc = device_limits(&cus, &lds);
+    if (rc) return rc;
+    // 16-bit copy of the hottest output-free rows for the hybrid placement
+    const uint32_t hot_rows =
+        std::min<uint32_t>(T.first_output, count_lds_limit(lds) / (T.sigma * 2u));
+    // (+2 entries: the LDS copy reads whole 32-bit words)
+    std::vector<uint16_t> hot16((size_t)std::max<uint32_t>(hot_rows, 1) * T.sigma + 2, 0);
+    for (size_t i = 0; i < (size_t)hot_rows * T.sigma; ++i)
+        hot16[i] = T.delta[i] < 0xFFFFu ? (uint16_t)T.delta[i] : (uint16_t)0xFFFFu;
+    d->hot16_rows = hot_rows;
     std::vector<uint32_t> rows(T.delta.size());
     const uint32_t row = T.sigma * 4u;
     for (size_t i = 0; i < rows.size(); ++i) rows[i] = T.delta[i] * row;
@@ -829,7 +851,8 @@ int upload_dict(ac_dict *d) {
     const size_t ids_bytes = std::max<size_t>(4, T.out_ids.size() * 4);
     if (hipMalloc((void **)&d->d_delta, rows.size() * 4) != hipSuccess ||
         hipMalloc((void **)&d->d_out_off, off_bytes) != hipSuccess ||
-        hipMalloc((void **)&d->d_out_ids, ids_bytes) != hipSuccess) {
+        hipMalloc((void **)&d->d_out_ids, ids_bytes) != hipSuccess ||
+        hipMalloc((void **)&d->d_hot16, hot16.size() * 2) != hipSuccess) {
         (void)hipGetLastError();
         release_dict(d);
         return AC_E_NOMEM;
@@ -838,7 +861,9 @@ int upload_dict(ac_dict *d) {
         hipMemcpy(d->d_out_off, T.out_off.data(), off_bytes, hipMemcpyHostToDevice) != hipSuccess ||
         (!T.out_ids.empty() &&
          hipMemcpy(d->d_out_ids, T.out_ids.data(), T.out_ids.size() * 4, hipMemcpyHostToDevice) !=
-             hipSuccess)) {
+             hipSuccess) ||
+        hipMemcpy(d->d_hot16, hot16.data(), hot16.size() * 2, hipMemcpyHostToDevice) !=
+            hipSuccess) {
         (void)hipGetLastError();
         release_dict(d);
         return AC_E_HIP;
@@ -851,7 +876,9 @@ void release_dict(ac_dict *d) {
     if (d->d_delta) (void)hipFree(d->d_delta);
     if (d->d_out_off) (void)hipFree(d->d_out_off);
     if (d->d_out_ids) (void)hipFree(d->d_out_ids);
+    if (d->d_hot16) (void)hipFree(d->d_hot16);
     d->d_delta = d->d_out_off = d->d_out_ids = nullptr;
+    d->d_hot16 = nullptr;
     (void)hipGetLastError();
 }
 
@@ -957,28 +984,36 @@ static uint64_t ws_layout(const Geom &g, bool batch, char *base, Workspace *w) {
     return o;
 }
 
-// Placement of one dictionary's table: returns hot bytes and lds_all.
-static void choose_placement(const ac_dict *d, uint32_t requested, uint32_t lds_limit,
-                             uint32_t *hot, uint32_t *lds_all) {
+// Placement of one dictionary's table for the count kernel: the LDS bytes
+// it copies, the hot bound of the table accessors and whether the whole
+// table is in LDS.
+struct Placement {
+    uint32_t hot = 0;        // see Inst::hot_bytes
+    uint32_t lds_all = 0;
+    uint32_t lds_bytes = 0;  // dynamic LDS the count kernel needs
+};
+
+static Placement choose_placement(const ac_dict *d, uint32_t requested, uint32_t lds_limit) {
+    Placement pl;
     const uint32_t tb = (uint32_t)d->table_bytes;
-    const uint32_t row = d->host.sigma * 4u;
+    const uint32_t sigma = d->host.sigma;
     uint32_t p = requested ? requested : d->placement;
     const bool fits = tb + kLdsPad <= lds_limit;
     if (p == AC_PLACE_AUTO) p = fits ? AC_PLACE_LDS : AC_PLACE_HYBRID;
     if (p == AC_PLACE_LDS && !fits) p = AC_PLACE_HYBRID;
+    if (p == AC_PLACE_HYBRID && d->hot16_rows == 0) p = AC_PLACE_GLOBAL;
     if (p == AC_PLACE_LDS) {
-        *hot = tb;
-        *lds_all = 1;
-    } else if (p == AC_PLACE_GLOBAL) {
-        *hot = 0;
-        *lds_all = 0;
-    } else {
-        uint32_t rows = d->hot_states ? d->hot_states : lds_limit / row;
-        uint64_t h = std::min<uint64_t>((uint64_t)rows * row, lds_limit / row * row);
-        if (h >= tb) h = tb;  // the whole table fits: still a split, all hot
-        *hot = (uint32_t)h;
-        *lds_all = 0;
+        pl.hot = tb;
+        pl.lds_all = 1;
+        pl.lds_bytes = tb + kLdsPad;
+    } else if (p == AC_PLACE_HYBRID) {
+        uint32_t rows = std::min<uint32_t>(d->hot16_rows, lds_limit / (sigma * 2u));
+        if (d->hot_states) rows = std::min(rows, d->hot_states);
+        pl.hot = rows * sigma * 4u;
+        pl.lds_bytes = (rows * sigma * 2u + 3u) & ~3u;
+        if (rows == 0) pl = Placement{};
     }
+    return pl;
 }
 
 static int resolve_geom(const ac_dict *const *dicts, const uint64_t *ns, uint32_t n_inst,
@@ -986,7 +1021,7 @@ static int resolve_geom(const ac_dict *const *dicts, const uint64_t *ns, uint32_
     uint32_t cus = 0, lds = 0;
     int rc = device_limits(&cus, &lds);
     if (rc != AC_OK) return rc;
-    const uint32_t lds_limit = lds - 512;  // static LDS of the count kernel
+    const uint32_t lds_limit = count_lds_limit(lds);
     uint32_t max_len = 1, max_out = 1;
     uint64_t total = 0;
     for (uint32_t i = 0; i < n_inst; ++i) {
@@ -1012,18 +1047,17 @@ static int resolve_geom(const ac_dict *const *dicts, const uint64_t *ns, uint32_
     uint32_t lds_bytes = 0;
     const uint32_t req = tune ? tune->placement : 0;
     if (req > AC_PLACE_HYBRID) return AC_E_INVALID;
-    for (uint32_t i = 0; i < n_inst; ++i) {
-        uint32_t hot, all;
-        choose_placement(dicts[i], req, lds_limit, &hot, &all);
-        lds_bytes = std::max(lds_bytes, all ? hot + kLdsPad : hot);
-    }
+    for (uint32_t i = 0; i < n_inst; ++i)
+        lds_bytes = std::max(lds_bytes, choose_placement(dicts[i], req, lds_limit).lds_bytes);
     g->lds_bytes = lds_bytes;
     uint32_t bpc = (tune && tune->blocks_per_cu) ? tune->blocks_per_cu
                                                   : std::max(1u, 2048u / g->threads);
     if (lds_bytes) bpc = std::max(1u, std::min(bpc, (lds + 0u) / (lds_bytes + 512u)));
     const uint64_t slots = (uint64_t)cus * bpc;
     if (!chunk) {
-        chunk = std::min<uint32_t>(1024, max_chunk);
+        // short chunks keep more lanes busy; 256 DNA bases (64 bytes packed)
+        // or 64 letters balance that against the warm-up before each chunk
+        chunk = std::min<uint32_t>(fmt == AC_TEXT_2BIT ? 256 : 64, max_chunk);
         while (chunk > kSeg && (total / chunk) / per_tile < slots) chunk /= 2;
     }
     g->chunk = chunk;
@@ -1062,7 +1096,11 @@ static void fill_inst(const ac_dict *d, const void *text, uint64_t n, uint32_t f
     I->table_bytes = (uint32_t)d->table_bytes;
     I->fo_state = d->host.first_output;
     I->fo_bytes = d->host.first_output * d->host.sigma * 4u;
-    choose_placement(d, req_place, lds_limit, &I->hot_bytes, &I->lds_all);
+    const Placement pl = choose_placement(d, req_place, lds_limit);
+    I->hot_bytes = pl.hot;
+    I->lds_all = pl.lds_all;
+    I->lds_bytes = pl.lds_bytes;
+    I->hot16 = d->d_hot16;
     const RowDiv rd = make_row_div(d->host.sigma);
     I->div_tz = rd.tz;
     I->div_inv = rd.inv;
@@ -1229,8 +1267,8 @@ int ac_scan(const ac_dict *d, const void *d_text, uint64_t n, uint32_t fmt, ac_m
     uint32_t cus, lds;
     device_limits(&cus, &lds);
     Inst I;
-    fill_inst(d, d_text, n, fmt, d_out, capacity, d_count, tune ? tune->placement : 0, lds - 512,
-              &I);
+    fill_inst(d, d_text, n, fmt, d_out, capacity, d_count, tune ? tune->placement : 0,
+              count_lds_limit(lds), &I);
     I.n_chunks = (uint32_t)g.n_chunks;
     I.n_tiles = (uint32_t)g.n_tiles;
     const uint64_t need = ws_layout(g, false, nullptr, nullptr);
