@@ -1,7 +1,7 @@
 #!/usr/bin/env python
 """Throughput of the Aho-Corasick scan on one MI355X.
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-batch] [--no-cpu]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-batch] [--no-cpu] [--no-serve]
 
 Workload (dna_dense): 268,435,456 DNA bases, GC content 0.4, 1 % of the text
 in poly-A runs of 50-500 bases; 10,000 patterns (A^8..A^16, 7,000 cut from
@@ -67,6 +67,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-requests", type=int, default=10_000,
+                    help="requests timed at the fixed arrival rate")
     ap.add_argument("--scale", type=float, default=1.0, help="shrink the workload (testing)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -236,6 +239,10 @@ def main():
     if not args.no_batch:
         result["batched"] = bench_batch(args, torch, ac, W, dev, stream)
 
+    # --------------------------------------------------------- serving
+    if not args.no_serve:
+        result["serve"] = bench_serve(args, torch, ac, W)
+
     del out
     print(json.dumps(result), flush=True)
 
@@ -319,6 +326,50 @@ def bench_batch(args, torch, ac, W, dev, stream):
             "speedup_batched_vs_plain": round(plain_ms / batch_ms, 2),
             "speedup_graph_vs_plain": round(plain_ms / graph_ms, 2),
             "identical_to_plain": bool(same and same_graph)}
+
+
+def bench_serve(args, torch, ac, W):
+    """Continuous batching under Poisson arrivals: the saturated request
+    rate R_sat (all requests queued at once), then latency percentiles at a
+    fixed arrival rate of 0.7 R_sat."""
+    from paper_1403_7294_amd.serve import Server, run_poisson
+    t0 = time.time()
+    n_sat = 2000
+    wl = W.serve(scale=args.scale, requests=n_sat + args.serve_requests)
+    letters = [W.to_ascii(t, W.DNA) for t in wl.texts]
+    srv = Server(wl.dictionaries, budget_bytes=8 << 30, max_batch=64, streams=2)
+    log(f"[bench] serve: {len(letters)} requests, {sum(len(t) for t in letters)} bases, "
+        f"8 dictionaries (setup {time.time() - t0:.1f} s)")
+    # warm-up, then saturation: everything queued at once
+    for f in [srv.submit(letters[k], int(wl.dict_of[k])) for k in range(64)]:
+        f.result()
+    srv.close()
+    srv = Server(wl.dictionaries, budget_bytes=8 << 30, max_batch=64, streams=2)
+    futs = [srv.submit(letters[k], int(wl.dict_of[k])) for k in range(n_sat)]
+    sat_res = [f.result() for f in futs]
+    sat = srv.close()
+    r_sat = n_sat / sat.wall_s
+    # the same requests alone, for equality (a sample)
+    same = True
+    for k in range(0, n_sat, n_sat // 25):
+        dev = torch.from_numpy(wl.texts[k].copy()).cuda()
+        out, total = ac.scan(srv.dicts[int(wl.dict_of[k])], dev, ac.AC_TEXT_U8)
+        same &= bool(np.array_equal(ac.match_keys(out), sat_res[k]))
+    rate = 0.7 * r_sat
+    srv = Server(wl.dictionaries, budget_bytes=8 << 30, max_batch=64, streams=2)
+    futs = run_poisson(srv, letters[n_sat:], wl.dict_of[n_sat:], wl.gaps[n_sat:], rate)
+    for f in futs:
+        f.result()
+    st = srv.close()
+    s = st.summary()
+    log(f"[bench] serve: R_sat {r_sat:.0f} req/s ({sat.bases / sat.wall_s / 1e9:.2f} Gbases/s); "
+        f"at {rate:.0f} req/s: p50 {s['p50_ms']} ms, p99 {s['p99_ms']} ms")
+    return {"workload": "serve: requests of log-uniform 1 K-1 M DNA letters, 8 dictionaries of "
+                        "1,000-50,000 random 10-30-mers, Poisson arrivals",
+            "saturated_requests_per_s": round(r_sat, 1),
+            "saturated_gbases_s": round(sat.bases / sat.wall_s / 1e9, 3),
+            "arrival_rate_per_s": round(rate, 1), **s,
+            "sample_equals_alone": same}
 
 
 if __name__ == "__main__":
