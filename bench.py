@@ -39,7 +39,7 @@ def log(*a):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("scan.hip", "batch.inc", "internal.h"):
+    for f in ("scan.hip", "batch.inc", "internal.h", "device_common.h"):
         with open(os.path.join(ROOT, "paper_1403_7294_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -71,6 +71,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=10_000,
                     help="requests timed at the fixed arrival rate")
     ap.add_argument("--scale", type=float, default=1.0, help="shrink the workload (testing)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy 1 GiB device to device 5 times: the reference kernel that "
+                         "scales the FETCH_SIZE / WRITE_SIZE counters to bytes")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs on a single MI355X "
@@ -85,6 +88,15 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
+    if args.calibrate_copy:
+        a = torch.ones(1 << 28, dtype=torch.int32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "device copy", "bytes_read": 1 << 30,
+                          "bytes_written": 1 << 30, "launches": 5}), flush=True)
+        return
 
     t0 = time.time()
     inst = W.dna_dense(scale=args.scale)
@@ -185,6 +197,15 @@ def main():
                 "traffic": measured_traffic(dom, "dna_dense"), "kernel": dom,
                 "kernel_avg_us": round(r["avg_us"], 2)}
 
+    cus, lds = ac.ac_device_info()
+    lds_limit = lds - 512
+    if info.table_bytes + 1024 <= lds_limit:
+        placement = "LDS (whole table)"
+    else:
+        rows = min(info.hot_states, lds_limit // (info.sigma * 2))
+        placement = (f"hybrid: {rows} most likely rows in LDS as 16-bit ids, "
+                     f"the rest from L2" if rows else "global (L1/L2)")
+
     # whole-step HBM roofline: letters read + packed write + packed read +
     # 8 B per match written
     step_bytes = n + 2 * ((n + 3) // 4) + 8.0 * total
@@ -201,8 +222,7 @@ def main():
                                "patterns (A^8..A^16, 7,000 cut 10-30, 2,991 random 10-30)",
                    "bases": n, "patterns": inst.patterns.count, "states": info.states,
                    "table_mib": round(info.table_bytes / 2**20, 3), "matches": total,
-                   "text_format": "2-bit", "placement": "global (L1/L2)" if
-                   info.table_bytes > 150 * 1024 else "LDS"},
+                   "text_format": "2-bit", "placement": placement},
         "roofline": roofline,
         "step_hbm_roofline": {"algorithmic_bytes": step_bytes,
                               "achieved_gbs": round(step_bytes / (step_ms * 1e-3) / 1e9, 1),

@@ -157,13 +157,17 @@ struct UTable {
         } else if constexpr (PLACE == PL_GLOBAL) {
             return buf_load(g, a);
         } else {
-            uint32_t v = 0xFFFFFFFFu;
-            if (a < hot) {
-                const uint32_t h = lds_load_u16(a >> 1);
-                if (h != 0xFFFFu) v = h * row;
-            }
-            if (v == 0xFFFFFFFFu) v = buf_load(g, a);
-            return v;
+            // rows past the LDS part go to the cache hierarchy first, so
+            // their latency overlaps the LDS read of the other lanes; a hot
+            // row entry 0xFFFF (target id beyond 16 bits) is read again from
+            // the 32-bit table
+            const bool in = a < hot;
+            uint32_t v1 = 0, v2 = 0;
+            if (!in) v1 = buf_load(g, a);
+            const uint32_t h = lds_load_u16((in ? a : 0u) >> 1);
+            const bool esc = in && h == 0xFFFFu;
+            if (esc) v2 = buf_load(g, a);
+            return in ? (esc ? v2 : h * row) : v1;
         }
     }
 };

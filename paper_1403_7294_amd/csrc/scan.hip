@@ -1037,7 +1037,10 @@ static int resolve_geom(const ac_dict *const *dicts, const uint64_t *ns, uint32_
     g->warm = (max_len - 1 + spw - 1) / spw;
     g->threads = (tune && tune->block_threads) ? tune->block_threads : 1024u;
     if (g->threads < 64 || g->threads > kMaxCountThreads || g->threads % 64) return AC_E_INVALID;
-    g->chains = (tune && tune->chains) ? tune->chains : 2u;
+    // two chains per lane for 2-bit text; one for byte text, whose
+    // dictionaries are wider rows (sigma 20) and whose lanes already walk
+    // short chunks
+    g->chains = (tune && tune->chains) ? tune->chains : (fmt == AC_TEXT_2BIT ? 2u : 1u);
     if (g->chains != 1 && g->chains != 2 && g->chains != 4) return AC_E_INVALID;
     const uint32_t per_tile = g->threads * g->chains;  // chunks per tile
     uint32_t chunk = tune ? tune->chunk : 0;
