@@ -363,11 +363,17 @@ def text_symbols(text_dev, fmt: int, n: Optional[int] = None) -> int:
 
 def scan(d: Dict, text_dev, fmt: int = AC_TEXT_U8, n: Optional[int] = None, capacity=None,
          tune=None, stream=None):
-    """Run ac_scan and return (matches[M, 2] int64 tensor of (pattern_id,
+    """Run ac_scan and return (matches[M, 2] int32 tensor of (pattern_id,
     end_pos) in (end, id) order, total M).  Re-runs once with an exact-size
-    buffer when the first guess overflows."""
+    buffer when the first guess overflows.  tune="auto" takes the launch
+    shape from the autotuner (timed once per shape key, then cached)."""
     import torch
     n = text_symbols(text_dev, fmt, n)
+    if isinstance(tune, str):
+        if tune != "auto":
+            raise ValueError("tune must be None, a dict, an ac_tune or 'auto'")
+        from .tune import autotune
+        tune = autotune(d, text_dev, n, fmt) if n else None
     dev = text_dev.device
     cap = capacity if capacity is not None else max(1024, n // 4)
     count = torch.zeros(1, dtype=torch.int64, device=dev)

@@ -785,6 +785,84 @@ __global__ __launch_bounds__(256) void k_encode(const uint8_t *__restrict__ in, 
     }
 }
 
+// DNA letters -> 2-bit codes, 64 letters per thread: four 16-byte
+// non-temporal loads, one 16-byte store.  Four letters are handled per 32-bit
+// word at once: code = ((ch>>1) ^ (ch>>2)) & 3 in every byte, then the four
+// 2-bit fields are gathered into one byte.  A byte is valid when (ch | 0x20)
+// is one of a c g t; the exact per-byte zero test
+// z(v) = ~(((v & 0x7F..) + 0x7F..) | v) & 0x80.. has no carries between
+// bytes.  Letters past n read as 0 through the buffer resource and are
+// neither counted nor stored.
+__device__ __forceinline__ uint32_t zero_bytes(uint32_t v) {
+    return ~(((v & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | v) & 0x80808080u;
+}
+
+__global__ __launch_bounds__(256) void k_encode_dna2(const uint8_t *__restrict__ in, uint64_t n,
+                                                     uint8_t *__restrict__ out,
+                                                     unsigned long long *invalid) {
+    constexpr int kNonTemporal = 2;
+    const uint64_t p = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 64u;
+    uint32_t bad = 0;
+    if (p < n) {
+        u32x4 v[4];
+        if (p + 64 <= n && (((uintptr_t)in) & 15) == 0) {
+            const rsrc_t r = make_rsrc(in, (uint32_t)n);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                v[q] = __builtin_amdgcn_raw_buffer_load_b128(r, (uint32_t)p + 16u * q, 0,
+                                                             kNonTemporal);
+        } else {
+            // the tail, or an input not 16-byte aligned: byte loads
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    uint32_t x = 0;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const uint64_t i = p + 16u * q + 4u * w + k;
+                        x |= (i < n ? (uint32_t)in[i] : 0u) << (8 * k);
+                    }
+                    v[q][w] = x;
+                }
+        }
+        u32x4 o;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            uint32_t packed = 0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const uint32_t x = v[q][w];
+                const uint32_t l = x | 0x20202020u;
+                const uint32_t ok = zero_bytes(l ^ 0x61616161u) | zero_bytes(l ^ 0x63636363u) |
+                                    zero_bytes(l ^ 0x67676767u) | zero_bytes(l ^ 0x74747474u);
+                const int64_t rem = (int64_t)n - (int64_t)(p + 16u * q + 4u * w);
+                const uint32_t live = rem >= 4 ? 0x80808080u
+                                      : rem <= 0 ? 0u
+                                                 : (uint32_t)((1ull << (8 * rem)) - 1u) & 0x80808080u;
+                bad += __builtin_popcount(~ok & live);
+                // invalid letters and letters past the end become code 0
+                const uint32_t t = ((x >> 1) ^ (x >> 2)) & ((ok & live) >> 7) * 3u;
+                packed |= ((t | (t >> 6) | (t >> 12) | (t >> 18)) & 0xFFu) << (8 * w);
+            }
+            o[q] = packed;
+        }
+        const uint64_t ob = p / 4;            // 16 output bytes per thread
+        const uint64_t nb = (n + 3) / 4;
+        if (ob + 16 <= nb && (((uintptr_t)(out + ob)) & 15) == 0) {
+            *(u32x4 *)(out + ob) = o;
+        } else {
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if (ob + i < nb) out[ob + i] = (uint8_t)(o[i >> 2] >> (8 * (i & 3)));
+        }
+    }
+    if (invalid) {
+        const uint32_t b = wave_sum_u32(bad);
+        if ((threadIdx.x & 63) == 0 && b) atomicAdd(invalid, (unsigned long long)b);
+    }
+}
+
 // ================================================================== host
 
 #define HIP_OK(x)                          \
@@ -1310,8 +1388,8 @@ int ac_encode(const uint8_t *d_ascii, uint64_t n, uint32_t alphabet, uint32_t fm
         const uint8_t *in = d_ascii;
         uint8_t *out = (uint8_t *)d_out;
         if (alphabet == AC_ALPHA_DNA && fmt == AC_TEXT_2BIT)
-            hipLaunchKernelGGL((k_encode<AC_ALPHA_DNA, AC_TEXT_2BIT>), dim3(blocks), dim3(256), 0, st,
-                               in, n, out, inv);
+            hipLaunchKernelGGL(k_encode_dna2, dim3((uint32_t)((n + 64 * 256 - 1) / (64 * 256))),
+                               dim3(256), 0, st, in, n, out, inv);
         else if (alphabet == AC_ALPHA_DNA)
             hipLaunchKernelGGL((k_encode<AC_ALPHA_DNA, AC_TEXT_U8>), dim3(blocks), dim3(256), 0, st,
                                in, n, out, inv);

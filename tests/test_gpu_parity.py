@@ -61,6 +61,30 @@ def test_encode_dna(n):
     assert np.array_equal(out2.cpu().numpy()[:(n + 3) // 4], oracle.pack2(want))
 
 
+@pytest.mark.parametrize("n,offset", [(1, 0), (63, 1), (64, 0), (65, 3), (4096, 0), (4097, 5),
+                                      ((1 << 20) + 13, 0), ((1 << 20) + 13, 7)])
+def test_encode_dna_invalid_and_unaligned(n, offset):
+    """Invalid letters become code 0 and are counted; the input may start at
+    any byte (a view into a larger tensor); ragged tails."""
+    torch = torch_cuda()
+    rng = W.rng_for(300 + n + offset)
+    letters = W.to_ascii(rng.integers(0, 4, size=n, dtype=np.uint8), W.DNA).copy()
+    letters[rng.random(n) < 0.3] |= 0x20
+    bad_at = rng.random(n) < 0.02
+    letters[bad_at] = rng.choice(np.frombuffer(b"NXnx*bB\x00\xff", np.uint8), int(bad_at.sum()))
+    clean = letters.copy()
+    clean[bad_at] = ord("A")
+    want = oracle.pack2(oracle.encode(clean, W.DNA))
+    big = torch.zeros(n + offset + 64, dtype=torch.uint8, device="cuda")
+    big[offset:offset + n] = torch.from_numpy(letters).cuda()
+    out = torch.full(((n + 3) // 4,), 77, dtype=torch.uint8, device="cuda")
+    bad = torch.full((1,), 5, dtype=torch.int64, device="cuda")
+    ac.ac_encode(big[offset:offset + n], ac.AC_ALPHA_DNA, ac.AC_TEXT_2BIT, out, bad)
+    torch.cuda.synchronize()
+    assert int(bad.item()) == int(bad_at.sum())
+    assert np.array_equal(out.cpu().numpy(), want)
+
+
 def test_encode_protein_and_invalid():
     torch = torch_cuda()
     rng = W.rng_for(7)
