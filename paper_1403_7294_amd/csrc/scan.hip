@@ -9,19 +9,20 @@
 // longest suffix of that prefix that is a trie prefix, and no trie prefix is
 // longer than max_len.  Every match is therefore reported by exactly one lane.
 //
-// A scan is four launches on the caller's stream:
-//   k_count     every lane walks its chunk once, one table lookup per symbol,
-//               and counts the matches ending in each 64-symbol segment (sum
-//               of the output-set sizes of the states entered).  For each
-//               segment with matches it stores the state on entry and the
-//               count; per chunk it stores the total and a segment bit mask.
-//   k_tile_scan one block: exclusive offsets of the per-tile totals.
-//   k_scatter   the work list: every segment with matches, with its entry
-//               state and its first output slot, in text order; segments with
-//               many matches are listed after the others so that lanes of a
-//               wave carry similar amounts of output.
-//   k_emit      one lane per listed segment walks its 64 symbols again from
-//               the stored state and writes each match at its final slot.
+// A scan is a short sequence of launches on the caller's stream:
+//   k_count      every lane walks its chunk once, one table lookup per
+//                symbol, and counts the matches ending in each 64-symbol
+//                segment (sum of the output-set sizes of the states entered).
+//                For each segment with matches it stores the count and the
+//                states entering its four 16-symbol quarters; per chunk it
+//                stores the total and a segment bit mask.
+//   k_tile_scan  one block: exclusive offsets of the per-tile totals.
+//   k_scatter    the work list: every segment with matches, with its
+//                quarter states and its first output slot, in text order;
+//                segments with many matches are listed after the others.
+//   k_emit       sparse segments: four lanes per segment re-walk its quarters
+//                from the stored states and write each match at its slot.
+//   k_emit_dense dense segments: one wave per segment, writes coalesced.
 // Matches therefore come out in (end position, pattern id) order with no
 // sort, and a too-small output buffer still receives the first matches.
 //
@@ -43,6 +44,7 @@
 namespace acx {
 
 constexpr uint32_t kSeg = AC_SEGMENT;     // symbols per segment
+constexpr uint32_t kQuarter = kSeg / 4;   // symbols per quarter segment
 constexpr uint32_t kMaxChunk = 2048;      // 32 segments: one bit each in a chunk mask
 constexpr uint32_t kDenseMatches = AC_DENSE_SEGMENT_MATCHES;  // listed last, one wave each
 constexpr uint32_t kLdsPad = 1024;        // zero bytes after an LDS table (u8 codes >= sigma)
@@ -107,7 +109,7 @@ __device__ __forceinline__ void walk_count(const UTable<PLACE> &tab, const UText
                                            const uint32_t *__restrict__ out_off, uint32_t fo,
                                            uint32_t fo_state, uint32_t tz, uint32_t inv,
                                            uint32_t chunk, uint32_t warm, const ChainIn (&in)[CH],
-                                           uint32_t *__restrict__ seg_state,
+                                           u32x4 *__restrict__ seg_state,
                                            uint32_t *__restrict__ seg_m, ChunkOut (&r)[CH]) {
     constexpr uint32_t SPW = Fmt<FMT>::SPW;
     constexpr uint32_t WPS = kSeg / SPW;  // text words per segment
@@ -142,12 +144,9 @@ __device__ __forceinline__ void walk_count(const UTable<PLACE> &tab, const UText
 #pragma unroll
     for (int c = 0; c < CH; ++c) nx[c] = txt.vec_once(w0[c]);
     for (uint32_t g = 0; g < spc; ++g) {
-        uint32_t s_entry[CH], sm[CH];
+        uint32_t qs[CH][4], sm[CH];
 #pragma unroll
-        for (int c = 0; c < CH; ++c) {
-            s_entry[c] = s[c];
-            sm[c] = 0;
-        }
+        for (int c = 0; c < CH; ++c) sm[c] = 0;
 #pragma unroll
         for (uint32_t v = 0; v < WPS; v += 4) {
             u32x4 x4[CH];
@@ -161,6 +160,11 @@ __device__ __forceinline__ void walk_count(const UTable<PLACE> &tab, const UText
             for (uint32_t q = 0; q < 4; ++q) {
                 uint32_t st[CH][SPW];
                 uint32_t acc[CH];
+                // the state on entry to each quarter segment
+                if (((v + q) * SPW) % kQuarter == 0) {
+#pragma unroll
+                    for (int c = 0; c < CH; ++c) qs[c][(v + q) * SPW / kQuarter] = s[c];
+                }
 #pragma unroll
                 for (int c = 0; c < CH; ++c) acc[c] = 0;
 #pragma unroll
@@ -192,7 +196,7 @@ __device__ __forceinline__ void walk_count(const UTable<PLACE> &tab, const UText
         for (int c = 0; c < CH; ++c) {
             if (sm[c]) {
                 r[c].mask |= 1u << g;
-                seg_state[in[c].seg0 + g] = s_entry[c];
+                seg_state[in[c].seg0 + g] = u32x4{qs[c][0], qs[c][1], qs[c][2], qs[c][3]};
                 seg_m[in[c].seg0 + g] = sm[c];
                 r[c].dense += sm[c] >= kDenseMatches;
             }
@@ -215,7 +219,7 @@ template <int FMT, bool BATCH, int CH>
 __global__ __launch_bounds__(kMaxCountThreads) void k_count(
     Inst single, const Inst *__restrict__ insts, const TileDesc *__restrict__ tiles,
     uint32_t n_tiles, uint32_t chunk, uint32_t warm, uint32_t *__restrict__ cnt,
-    uint32_t *__restrict__ mask, uint32_t *__restrict__ seg_state, uint32_t *__restrict__ seg_m,
+    uint32_t *__restrict__ mask, u32x4 *__restrict__ seg_state, uint32_t *__restrict__ seg_m,
     unsigned long long *__restrict__ tile_m, uint32_t *__restrict__ tile_zs,
     uint32_t *__restrict__ tile_zd) {
     __shared__ unsigned long long red_a[16];
@@ -367,11 +371,11 @@ template <bool BATCH>
 __global__ __launch_bounds__(kMaxCountThreads) void k_scatter(
     Inst single, const Inst *__restrict__ insts, const TileDesc *__restrict__ tiles,
     uint32_t chunk, uint32_t per, const uint32_t *__restrict__ cnt,
-    const uint32_t *__restrict__ mask, const uint32_t *__restrict__ seg_state,
+    const uint32_t *__restrict__ mask, const u32x4 *__restrict__ seg_state,
     const uint32_t *__restrict__ seg_m, const unsigned long long *__restrict__ tile_moff,
     const uint32_t *__restrict__ tile_zsoff, const uint32_t *__restrict__ tile_zdoff,
     const unsigned long long *__restrict__ totals, uint32_t *__restrict__ list_seg,
-    uint32_t *__restrict__ list_state, unsigned long long *__restrict__ list_moff,
+    u32x4 *__restrict__ list_state, unsigned long long *__restrict__ list_moff,
     uint32_t *__restrict__ list_inst) {
     const uint32_t t = blockIdx.x;
     const uint32_t spc = chunk / kSeg;
@@ -464,118 +468,105 @@ __device__ __forceinline__ void write_set(ac_match *__restrict__ out, unsigned l
     }
 }
 
-// Sparse part of the work list: one lane per listed segment walks its 64
-// symbols from the stored entry state and writes the output set of every
-// state it enters, in id order, at consecutive slots from the segment's
-// first slot.
-//
-// Stores are kept out of the walk: on gfx9 a wave's wait for a load also
-// waits for its earlier stores, so a store in the middle of the dependent
-// lookup chain would stall every later step.  The walk therefore records up
-// to kEvents output events (state, position) per lane in LDS, and the
-// writes follow the walk.  A word that reaches an output state is walked a
-// second time to record its events, so the common word costs one lookup per
-// symbol and a max.  Lanes with more than kEvents events walk the segment a
-// second time for the rest (rare: a segment listed as sparse has fewer than
-// kDenseMatches matches).
-constexpr uint32_t kEvents = 16;
-
+// Sparse part of the work list: four lanes per listed segment, lane q
+// walking quarter q (16 symbols) from the state the count pass stored for
+// it, so a segment costs 16 dependent lookups instead of 64.  A lane records
+// its output events (state, position) in LDS during the walk -- at most one
+// per position, so 16 slots always suffice -- and writes after the walk:
+// on gfx9 a wave's wait for a load also waits for its earlier stores, so a
+// store inside the lookup chain would stall every later step.  The four
+// lanes of a segment are adjacent in the wave; the offset of each quarter's
+// first match is an exclusive sum of the quarters' match counts over those
+// four lanes.  Within a quarter, events are written in position order and
+// each output set in id order, which is the (end, id) order.
 template <int FMT, bool BATCH>
 __global__ __launch_bounds__(kEmitThreads) void k_emit(
     Inst single, const Inst *__restrict__ insts, const uint32_t *__restrict__ list_seg,
-    const uint32_t *__restrict__ list_state, const unsigned long long *__restrict__ list_moff,
+    const u32x4 *__restrict__ list_state, const unsigned long long *__restrict__ list_moff,
     const uint32_t *__restrict__ list_inst, const unsigned long long *__restrict__ totals) {
     constexpr uint32_t SPW = Fmt<FMT>::SPW;
     constexpr uint32_t WPS = kSeg / SPW;
-    __shared__ uint32_t ev_state[kEvents][kEmitThreads];
-    __shared__ uint8_t ev_pos[kEvents][kEmitThreads];
+    constexpr uint32_t WPQ = kQuarter / SPW;  // text words per quarter
+    __shared__ uint32_t ev_state[kQuarter][kEmitThreads];
+    __shared__ uint8_t ev_pos[kQuarter][kEmitThreads];
     const uint32_t tid = threadIdx.x;
-    const uint32_t total = (uint32_t)totals[1];
-    for (uint32_t idx = blockIdx.x * blockDim.x + tid; idx < total;
-         idx += gridDim.x * blockDim.x) {
-        const uint32_t inst = BATCH ? list_inst[idx] : 0u;
-        const Inst &I = BATCH ? insts[inst] : single;
-        const uint32_t seg = list_seg[idx];
-        const uint32_t s0 = list_state[idx];
-        const unsigned long long off0 = list_moff[idx];
-        const uint32_t e0 = seg * kSeg;
-        const uint32_t lim = min(kSeg, I.n - e0);
-        const uint32_t fo = I.fo_bytes, fos = I.fo_state, tz = I.div_tz, inv = I.div_inv;
-        const uint32_t *out_off = I.out_off;
-        const uint32_t *ids = I.out_ids;
-        ac_match *out = I.out;
-        const unsigned long long cap = I.capacity;
-        auto body = [&](const auto &tab, const auto &txt) {
-            // walk, recording output events
-            uint32_t s = s0, ne = 0;
-#pragma unroll 1
-            for (uint32_t w = 0; w < WPS; ++w) {
-                const uint32_t x = txt.word((int)(seg * WPS + w));
-                const uint32_t s_in = s;
-                uint32_t acc = 0;
+    const uint32_t lane = tid & 63;
+    const uint32_t q = tid & 3;
+    const uint32_t items = 4u * (uint32_t)totals[1];
+    // the loop bound is uniform over the wave, so every lane of a segment's
+    // group takes part in the group's shuffles
+    for (uint32_t base = blockIdx.x * blockDim.x + (tid - lane); base < items;
+         base += gridDim.x * blockDim.x) {
+        const uint32_t li = base + lane;
+        const bool act = li < items;
+        const uint32_t idx = act ? li >> 2 : 0u;
+        uint32_t ne = 0, matches = 0;
+        uint32_t e0 = 0;
+        unsigned long long off0 = 0;
+        if (act) {
+            const uint32_t inst = BATCH ? list_inst[idx] : 0u;
+            const Inst &I = BATCH ? insts[inst] : single;
+            const uint32_t seg = list_seg[idx];
+            const u32x4 qs = list_state[idx];
+            off0 = list_moff[idx];
+            e0 = seg * kSeg;
+            const uint32_t lim = min(kSeg, I.n - e0);
+            const uint32_t fo = I.fo_bytes, fos = I.fo_state, tz = I.div_tz, inv = I.div_inv;
+            const uint32_t *out_off = I.out_off;
+            auto walk = [&](const auto &tab, const auto &txt) {
+                uint32_t st = q == 0 ? qs.x : q == 1 ? qs.y : q == 2 ? qs.z : qs.w;
 #pragma unroll
-                for (uint32_t k = 0; k < SPW; ++k) {
-                    s = tab(s + sym_bytes<FMT>(x, k));
-                    acc = acc > s ? acc : s;
-                }
-                if (acc < fo) continue;
-                uint32_t r = s_in;
-#pragma unroll 1
-                for (uint32_t k = 0; k < SPW; ++k) {
-                    r = tab(r + sym_bytes<FMT>(x, k));
-                    const uint32_t p = w * SPW + k;
-                    if (r >= fo && p < lim) {
-                        if (ne < kEvents) {
-                            ev_state[ne][tid] = r;
+                for (uint32_t w = 0; w < WPQ; ++w) {
+                    const uint32_t x = txt.word((int)(seg * WPS + q * WPQ + w));
+#pragma unroll
+                    for (uint32_t k = 0; k < SPW; ++k) {
+                        st = tab(st + sym_bytes<FMT>(x, k));
+                        const uint32_t p = q * kQuarter + w * SPW + k;
+                        if (st >= fo && p < lim) {
+                            ev_state[ne][tid] = st;
                             ev_pos[ne][tid] = (uint8_t)p;
+                            ++ne;
                         }
-                        ++ne;
                     }
                 }
+            };
+            if constexpr (BATCH) {
+                walk(LTable{I.delta, I.table_bytes}, LText{(const uint32_t *)I.text, I.text_bytes4});
+            } else {
+                walk(UTable<PL_GLOBAL>{make_rsrc(single.delta, single.table_bytes), 0, 0},
+                     UText{make_rsrc(single.text, single.text_bytes4), single.text_bytes4});
             }
-            // write the recorded events
-            unsigned long long off = off0;
-            const uint32_t nrec = ne < kEvents ? ne : kEvents;
-            for (uint32_t j = 0; j < nrec; ++j) {
-                const uint32_t r = ev_state[j][tid];
-                const uint32_t p = ev_pos[j][tid];
-                const uint32_t o = row_state(r, tz, inv) - fos;
+            for (uint32_t j = 0; j < ne; ++j) {
+                const uint32_t o = row_state(ev_state[j][tid], tz, inv) - fos;
+                matches += out_off[o + 1] - out_off[o];
+            }
+        }
+        // exclusive sum over the quarters before this one
+        const uint32_t m1 = __shfl_up(matches, 1, 64);
+        const uint32_t m2 = __shfl_up(matches, 2, 64);
+        const uint32_t m3 = __shfl_up(matches, 3, 64);
+        const uint32_t before = (q >= 1 ? m1 : 0u) + (q >= 2 ? m2 : 0u) + (q >= 3 ? m3 : 0u);
+        if (act && ne) {
+            const Inst &I = BATCH ? insts[list_inst[idx]] : single;
+            const uint32_t fos = I.fo_state, tz = I.div_tz, inv = I.div_inv;
+            const uint32_t *out_off = I.out_off;
+            unsigned long long off = off0 + before;
+            for (uint32_t j = 0; j < ne; ++j) {
+                const uint32_t o = row_state(ev_state[j][tid], tz, inv) - fos;
                 const uint32_t a = out_off[o], len = out_off[o + 1] - a;
-                write_set(out, off, cap, ids, a, len, e0 + p);
+                write_set(I.out, off, I.capacity, I.out_ids, a, len, e0 + ev_pos[j][tid]);
                 off += len;
             }
-            if (ne <= kEvents) return;
-            // more events than recorded: walk again, writing from event kEvents on
-            uint32_t t = s0, seen = 0;
-#pragma unroll 1
-            for (uint32_t p = 0; p < lim; ++p) {
-                const uint32_t x = txt.word((int)(seg * WPS + p / SPW));
-                t = tab(t + sym_bytes<FMT>(x, p % SPW));
-                if (t >= fo) {
-                    if (seen >= kEvents) {
-                        const uint32_t o = row_state(t, tz, inv) - fos;
-                        const uint32_t a = out_off[o], len = out_off[o + 1] - a;
-                        write_set(out, off, cap, ids, a, len, e0 + p);
-                        off += len;
-                    }
-                    ++seen;
-                }
-            }
-        };
-        if constexpr (BATCH) {
-            body(LTable{I.delta, I.table_bytes}, LText{(const uint32_t *)I.text, I.text_bytes4});
-        } else {
-            body(UTable<PL_GLOBAL>{make_rsrc(single.delta, single.table_bytes), 0, 0},
-                 UText{make_rsrc(single.text, single.text_bytes4), single.text_bytes4});
         }
     }
 }
 
-// Dense part of the work list: one wave per listed segment.  The wave walks
-// the segment once (all lanes together, so each lookup is one broadcast
-// read); lane k keeps the state entered at position k and, before any store
-// is issued, loads where that state's output set starts and how long it is.
-// A prefix sum over the wave gives every position its first slot.
+// Dense part of the work list: one wave per listed segment.  Four groups of
+// 16 lanes walk the segment's four quarters at once, each from the state the
+// count pass stored for its quarter (16 dependent lookups per segment); lane
+// k keeps the state entered at position k and, before any store is issued,
+// loads where that state's output set starts and how long it is.  A prefix
+// sum over the wave gives every position its first slot.
 //
 // The positions are then written as runs of equal states (a poly-A run is
 // one long run of the deepest all-A state): a run of r positions whose set
@@ -592,10 +583,11 @@ constexpr uint32_t kDenseThreads = 256;
 template <int FMT, bool BATCH>
 __global__ __launch_bounds__(kDenseThreads) void k_emit_dense(
     Inst single, const Inst *__restrict__ insts, const uint32_t *__restrict__ list_seg,
-    const uint32_t *__restrict__ list_state, const unsigned long long *__restrict__ list_moff,
+    const u32x4 *__restrict__ list_state, const unsigned long long *__restrict__ list_moff,
     const uint32_t *__restrict__ list_inst, const unsigned long long *__restrict__ totals) {
     constexpr uint32_t SPW = Fmt<FMT>::SPW;
     constexpr uint32_t WPS = kSeg / SPW;
+    constexpr uint32_t WPQ = kQuarter / SPW;  // text words per quarter
     const uint32_t n_sparse = (uint32_t)totals[1];
     const uint32_t n_dense = (uint32_t)totals[2];
     const uint32_t lane = threadIdx.x & 63;
@@ -606,7 +598,11 @@ __global__ __launch_bounds__(kDenseThreads) void k_emit_dense(
         const uint32_t inst = BATCH ? uniform(list_inst[idx]) : 0u;
         const Inst &I = BATCH ? insts[inst] : single;
         const uint32_t seg = uniform(list_seg[idx]);
-        uint32_t s = uniform(list_state[idx]);
+        const u32x4 qs = list_state[idx];
+        const uint32_t gq = lane / kQuarter;  // the quarter this lane's group walks
+        const uint32_t q0 = uniform(qs.x), q1 = uniform(qs.y), q2 = uniform(qs.z),
+                       q3 = uniform(qs.w);
+        uint32_t s = gq == 0 ? q0 : gq == 1 ? q1 : gq == 2 ? q2 : q3;
         const unsigned long long off0 = uniform(list_moff[idx]);
         const uint32_t e0 = seg * kSeg;
         const uint32_t lim = min(kSeg, uniform(I.n) - e0);
@@ -620,17 +616,16 @@ __global__ __launch_bounds__(kDenseThreads) void k_emit_dense(
         if (off0 >= cap) continue;
         const UTable<PL_GLOBAL> tab{make_rsrc(uniform(I.delta), tb), 0, 0};
         const UText txt{make_rsrc(uniform(I.text), tb4), tb4};
+        // four groups of 16 lanes walk the four quarters at once; lane
+        // 16 g + k keeps the state entered at position k of quarter g
         uint32_t mine = 0;
 #pragma unroll
-        for (uint32_t v = 0; v < WPS; v += 4) {
-            const u32x4 x4 = txt.vec(seg * WPS + v);
+        for (uint32_t w = 0; w < WPQ; ++w) {
+            const uint32_t x = txt.word((int)(seg * WPS + gq * WPQ + w));
 #pragma unroll
-            for (uint32_t q = 0; q < 4; ++q) {
-#pragma unroll
-                for (uint32_t k = 0; k < SPW; ++k) {
-                    s = tab(s + sym_bytes<FMT>(x4[q], k));
-                    if (lane == (v + q) * SPW + k) mine = s;
-                }
+            for (uint32_t k = 0; k < SPW; ++k) {
+                s = tab(s + sym_bytes<FMT>(x, k));
+                if (lane % kQuarter == w * SPW + k) mine = s;
             }
         }
         const bool has = mine >= fo && lane < lim;
@@ -1024,13 +1019,15 @@ struct Geom {
 
 struct Workspace {
     uint32_t *cnt, *mask;                 // per chunk
-    uint32_t *seg_state, *seg_m;          // per segment (written where matches exist)
+    u32x4 *seg_state;                     // per segment: states entering its quarters
+    uint32_t *seg_m;                      // per segment: matches (written where > 0)
     unsigned long long *tile_m;           // per tile
     uint32_t *tile_zs, *tile_zd;
     unsigned long long *tile_moff;        // per tile, + grand total
     uint32_t *tile_zsoff, *tile_zdoff;
     unsigned long long *totals;           // matches, sparse segments, dense segments
-    uint32_t *list_seg, *list_state, *list_inst;  // work list of segments
+    uint32_t *list_seg, *list_inst;       // work list of segments
+    u32x4 *list_state;
     unsigned long long *list_moff;
 };
 
@@ -1045,7 +1042,7 @@ static uint64_t ws_layout(const Geom &g, bool batch, char *base, Workspace *w) {
     Workspace t;
     t.cnt = (uint32_t *)take(4 * C);
     t.mask = (uint32_t *)take(4 * C);
-    t.seg_state = (uint32_t *)take(4 * S);
+    t.seg_state = (u32x4 *)take(16 * S);
     t.seg_m = (uint32_t *)take(4 * S);
     t.tile_m = (unsigned long long *)take(8 * T);
     t.tile_zs = (uint32_t *)take(4 * T);
@@ -1055,7 +1052,7 @@ static uint64_t ws_layout(const Geom &g, bool batch, char *base, Workspace *w) {
     t.tile_zdoff = (uint32_t *)take(4 * (T + 1));
     t.totals = (unsigned long long *)take(32);
     t.list_seg = (uint32_t *)take(4 * S);
-    t.list_state = (uint32_t *)take(4 * S);
+    t.list_state = (u32x4 *)take(16 * S);
     t.list_inst = batch ? (uint32_t *)take(4 * S) : nullptr;
     t.list_moff = (unsigned long long *)take(8 * S);
     if (w) *w = t;
@@ -1154,7 +1151,7 @@ static int resolve_geom(const ac_dict *const *dicts, const uint64_t *ns, uint32_
     // persistent emit grids, no larger than the work list can ever need
     const uint64_t segs = g->n_segs();
     g->grid_emit = (uint32_t)std::max<uint64_t>(
-        1, std::min<uint64_t>((uint64_t)cus * 8, (segs + kEmitThreads - 1) / kEmitThreads));
+        1, std::min<uint64_t>((uint64_t)cus * 8, (4 * segs + kEmitThreads - 1) / kEmitThreads));
     g->grid_dense = (uint32_t)std::max<uint64_t>(
         1, std::min<uint64_t>((uint64_t)cus * 8, (segs + kDenseThreads / 64 - 1) / (kDenseThreads / 64)));
     return AC_OK;
