@@ -67,12 +67,16 @@ extern "C" {
 #define AC_PLACE_LDS 1      /* whole table in LDS (must fit)                */
 #define AC_PLACE_GLOBAL 2   /* table read through L1/L2 from HBM            */
 #define AC_PLACE_HYBRID 3   /* most visited rows in LDS as 16-bit ids, rest global */
+#define AC_PLACE_LDS2 4     /* DNA in 2-bit text only: transitions over two
+                             * symbols at once (states x 16 entries) in LDS,
+                             * one lookup per two bases; needs states * 64
+                             * bytes of LDS, else falls back to AC_PLACE_LDS */
 
 #define AC_BUILD_HOST_ONLY 1u /* compile tables on the host only (no GPU)   */
 
 /* Work units of the scan: a segment is AC_SEGMENT text symbols; segments
  * with at least AC_DENSE_SEGMENT_MATCHES matches are written by a whole
- * wavefront each (the AC_K_EMIT_DENSE kernel), the others by one lane. */
+ * wavefront each (the AC_K_EMIT_DENSE kernel), the others by four lanes. */
 #define AC_SEGMENT 64
 #define AC_DENSE_SEGMENT_MATCHES 256
 

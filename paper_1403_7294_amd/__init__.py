@@ -39,7 +39,7 @@ AC_TEXT_U8 = 0
 AC_TEXT_2BIT = 1
 AC_ALPHA_DNA = 0
 AC_ALPHA_PROTEIN = 1
-AC_PLACE_AUTO, AC_PLACE_LDS, AC_PLACE_GLOBAL, AC_PLACE_HYBRID = 0, 1, 2, 3
+AC_PLACE_AUTO, AC_PLACE_LDS, AC_PLACE_GLOBAL, AC_PLACE_HYBRID, AC_PLACE_LDS2 = 0, 1, 2, 3, 4
 AC_BUILD_HOST_ONLY = 1
 AC_SEGMENT = 64
 AC_DENSE_SEGMENT_MATCHES = 256

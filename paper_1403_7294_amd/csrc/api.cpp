@@ -16,7 +16,7 @@ int ac_build(const uint8_t *symbols, const uint64_t *offsets, uint32_t n_pattern
     *out = nullptr;
     ac_build_opts o = {4, AC_PLACE_AUTO, 0, 0};
     if (opts) o = *opts;
-    if (o.placement > AC_PLACE_HYBRID || (o.flags & ~AC_BUILD_HOST_ONLY)) return AC_E_INVALID;
+    if (o.placement > AC_PLACE_LDS2 || (o.flags & ~AC_BUILD_HOST_ONLY)) return AC_E_INVALID;
     ac_dict *d = new (std::nothrow) ac_dict();
     if (!d) return AC_E_NOMEM;
     const auto t0 = std::chrono::steady_clock::now();

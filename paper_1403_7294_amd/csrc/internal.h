@@ -60,6 +60,11 @@ struct ac_dict {
     uint32_t *d_out_ids = nullptr;
     uint16_t *d_hot16 = nullptr;  // first hot16_rows rows as 16-bit ids (0xFFFF: see table)
     uint32_t hot16_rows = 0;
+    // sigma 4 only, when it fits LDS: transitions over two symbols,
+    // states x 16 entries; entry = next row offset (next * 64), bit 31 set
+    // when the state after the first symbol has an output set
+    uint32_t *d_delta2 = nullptr;
+    uint32_t delta2_bytes = 0;
     uint64_t table_bytes = 0;
 };
 

@@ -75,6 +75,9 @@ struct Inst {
     uint32_t n_tiles;
     uint32_t div_tz, div_inv;
     uint32_t sigma;
+    const uint32_t *delta2;  // two-symbol transitions (stride2 only)
+    uint32_t stride2;        // 1: the count pass walks two symbols per lookup from LDS
+    uint32_t fo2_bytes;      // first output row offset in the two-symbol table
 };
 
 struct TileDesc {
@@ -140,9 +143,15 @@ __device__ __forceinline__ void walk_count(const UTable<PLACE> &tab, const UText
             }
         }
     }
-    u32x4 nx[CH];
+    // text vectors (4 words) in flight ahead of the walk: 128 bases of
+    // 2-bit text, 64 byte symbols
+    constexpr uint32_t PD = FMT == AC_TEXT_2BIT ? 2 : 4;
+    u32x4 nx[CH][PD];
 #pragma unroll
-    for (int c = 0; c < CH; ++c) nx[c] = txt.vec_once(w0[c]);
+    for (int c = 0; c < CH; ++c)
+#pragma unroll
+        for (uint32_t p = 0; p < PD; ++p)
+            nx[c][p] = 4 * p < wpc ? txt.vec_once(w0[c] + 4 * p) : u32x4{0, 0, 0, 0};
     for (uint32_t g = 0; g < spc; ++g) {
         uint32_t qs[CH][4], sm[CH];
 #pragma unroll
@@ -150,11 +159,13 @@ __device__ __forceinline__ void walk_count(const UTable<PLACE> &tab, const UText
 #pragma unroll
         for (uint32_t v = 0; v < WPS; v += 4) {
             u32x4 x4[CH];
-            const uint32_t wn = g * WPS + v + 4;
+            const uint32_t wn = g * WPS + v + 4 * PD;
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
-                x4[c] = nx[c];
-                if (wn < wpc) nx[c] = txt.vec_once(w0[c] + wn);
+                x4[c] = nx[c][0];
+#pragma unroll
+                for (uint32_t p = 0; p + 1 < PD; ++p) nx[c][p] = nx[c][p + 1];
+                if (wn < wpc) nx[c][PD - 1] = txt.vec_once(w0[c] + wn);
             }
 #pragma unroll
             for (uint32_t q = 0; q < 4; ++q) {
@@ -205,11 +216,137 @@ __device__ __forceinline__ void walk_count(const UTable<PLACE> &tab, const UText
     }
 }
 
-// Copy the LDS part of a table (zero-filled past the table's end).
+// The same walk over 2-bit DNA with the two-symbol table in LDS: one lookup
+// per two bases.  An entry is the row offset of the state after both
+// symbols (state * 64) with bit 31 set when the state after the first symbol
+// has an output set, so a running max over the entries of a word exceeds the
+// first output row offset exactly when some state entered in the word has
+// an output set.  Such a word (rare) is walked again one symbol at a time
+// through the single-symbol table to add the output-set sizes.  Quarter
+// states are stored as single-symbol row offsets, which the emit kernels
+// read.
+template <int CH>
+__device__ __forceinline__ void walk_count2(rsrc_t g1, const UText &txt,
+                                            const uint32_t *__restrict__ out_off, uint32_t fo1,
+                                            uint32_t fo2, uint32_t fo_state, uint32_t tz,
+                                            uint32_t inv, uint32_t chunk, uint32_t warm,
+                                            const ChainIn (&in)[CH], u32x4 *__restrict__ seg_state,
+                                            uint32_t *__restrict__ seg_m, ChunkOut (&r)[CH]) {
+    constexpr uint32_t SPW = 16;          // bases per text word
+    constexpr uint32_t WPS = kSeg / SPW;  // words per segment (4)
+    constexpr uint32_t kMask = 0x7FFFFFFFu;
+    const uint32_t wpc = chunk / SPW, spc = chunk / kSeg;
+    uint32_t s[CH], w0[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+        w0[c] = in[c].j * wpc;
+        s[c] = 0;
+        r[c] = ChunkOut{0, 0, 0};
+    }
+    for (uint32_t i = 0; i < warm; ++i) {
+        uint32_t x[CH];
+        bool live[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int w = (int)w0[c] - (int)warm + (int)i;
+            x[c] = txt.word(w);
+            live[c] = w >= 0;
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < SPW / 2; ++k) {
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const uint32_t ns = lds_load(s[c] + ((x[c] >> (4 * k)) & 15u) * 4u) & kMask;
+                s[c] = live[c] ? ns : s[c];
+            }
+        }
+    }
+    constexpr uint32_t PD = 2;  // segments of text in flight ahead of the walk
+    u32x4 nx[CH][PD];
+#pragma unroll
+    for (int c = 0; c < CH; ++c)
+#pragma unroll
+        for (uint32_t p = 0; p < PD; ++p)
+            nx[c][p] = 4 * p < wpc ? txt.vec_once(w0[c] + 4 * p) : u32x4{0, 0, 0, 0};
+    for (uint32_t g = 0; g < spc; ++g) {
+        uint32_t qs[CH][4], sm[CH];
+        u32x4 x4[CH];
+        const uint32_t wn = g * WPS + 4 * PD;
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            sm[c] = 0;
+            x4[c] = nx[c][0];
+#pragma unroll
+            for (uint32_t p = 0; p + 1 < PD; ++p) nx[c][p] = nx[c][p + 1];
+            if (wn < wpc) nx[c][PD - 1] = txt.vec_once(w0[c] + wn);
+        }
+#pragma unroll
+        for (uint32_t q = 0; q < WPS; ++q) {
+            uint32_t acc[CH], s_in[CH];
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                s_in[c] = s[c];
+                qs[c][q] = s[c] >> 2;  // single-symbol row offset
+                acc[c] = 0;
+            }
+#pragma unroll
+            for (uint32_t k = 0; k < SPW / 2; ++k) {
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    const uint32_t e = lds_load(s[c] + ((x4[c][q] >> (4 * k)) & 15u) * 4u);
+                    acc[c] = acc[c] > e ? acc[c] : e;
+                    s[c] = e & kMask;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                if (acc[c] >= fo2) {
+                    const uint32_t p0 = (g * WPS + q) * SPW;
+                    uint32_t t = s_in[c] >> 2;
+                    for (uint32_t k = 0; k < SPW; ++k) {
+                        t = buf_load(g1, t + ((x4[c][q] >> (2 * k)) & 3u) * 4u);
+                        if (t >= fo1 && p0 + k < in[c].lim) {
+                            const uint32_t o = row_state(t, tz, inv) - fo_state;
+                            sm[c] += out_off[o + 1] - out_off[o];
+                        }
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            if (sm[c]) {
+                r[c].mask |= 1u << g;
+                seg_state[in[c].seg0 + g] = u32x4{qs[c][0], qs[c][1], qs[c][2], qs[c][3]};
+                seg_m[in[c].seg0 + g] = sm[c];
+                r[c].dense += sm[c] >= kDenseMatches;
+            }
+            r[c].m += sm[c];
+        }
+    }
+}
+
+// Copy the LDS part of a table (zero-filled past the table's end).  Each
+// thread has 16 dword loads in flight before its first LDS write, so a
+// 160 KB table takes a few memory latencies rather than one per 4 KB.
 __device__ __forceinline__ void load_lds_table(rsrc_t g, uint32_t bytes) {
     extern __shared__ uint32_t dyn_smem[];
-    for (uint32_t o = threadIdx.x * 4u; o < bytes; o += blockDim.x * 4u)
-        ((lds_u32 *)dyn_smem)[o >> 2] = buf_load(g, o);
+    constexpr uint32_t U = 4;
+    const uint32_t step = blockDim.x * 16u;
+    for (uint32_t base = threadIdx.x * 16u; base < bytes; base += U * step) {
+        uint32_t v[U][4];
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u)
+#pragma unroll
+            for (uint32_t i = 0; i < 4; ++i) v[u][i] = buf_load(g, base + u * step + 4u * i);
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u)
+#pragma unroll
+            for (uint32_t i = 0; i < 4; ++i) {
+                const uint32_t o = base + u * step + 4u * i;
+                if (o < bytes) ((lds_u32 *)dyn_smem)[o >> 2] = v[u][i];
+            }
+    }
 }
 
 // Persistent count kernel.  Block b takes a contiguous range of tiles; a
@@ -249,7 +386,9 @@ __global__ __launch_bounds__(kMaxCountThreads) void k_count(
             if (hot) {
                 const uint32_t lb = uniform(I.lds_bytes);
                 __syncthreads();
-                if (lds_all)
+                if (uniform(I.stride2))
+                    load_lds_table(make_rsrc(uniform(I.delta2), lb), lb);
+                else if (lds_all)
                     load_lds_table(gtab, lb);
                 else
                     load_lds_table(make_rsrc(uniform(I.hot16), lb), lb);
@@ -275,7 +414,16 @@ __global__ __launch_bounds__(kMaxCountThreads) void k_count(
             in[c].seg0 = (cbase + in[c].j) * spc;
         }
         ChunkOut co[CH];
-        if (lds_all) {
+        bool done = false;
+        if constexpr (FMT == AC_TEXT_2BIT) {
+            if (uniform(I.stride2)) {
+                walk_count2<CH>(gtab, txt, out_off, fo, uniform(I.fo2_bytes), fos, tz, inv, chunk,
+                                warm, in, seg_state, seg_m, co);
+                done = true;
+            }
+        }
+        if (done) {
+        } else if (lds_all) {
             walk_count<FMT, PL_LDS, CH>(UTable<PL_LDS>{gtab, hot, row}, txt, out_off, fo, fos, tz, inv,
                                         chunk, warm, in, seg_state, seg_m, co);
         } else if (hot == 0) {
@@ -917,6 +1065,18 @@ int upload_dict(ac_dict *d) {
     for (size_t i = 0; i < (size_t)hot_rows * T.sigma; ++i)
         hot16[i] = T.delta[i] < 0xFFFFu ? (uint16_t)T.delta[i] : (uint16_t)0xFFFFu;
     d->hot16_rows = hot_rows;
+    // two-symbol table, when it fits the count kernel's LDS
+    std::vector<uint32_t> d2;
+    if (T.sigma == 4 && (uint64_t)T.states * 64u <= count_lds_limit(lds)) {
+        d2.resize((size_t)T.states * 16);
+        for (uint32_t s = 0; s < T.states; ++s)
+            for (uint32_t c1 = 0; c1 < 4; ++c1) {
+                const uint32_t t1 = T.delta[(size_t)s * 4 + c1];
+                const uint32_t flag = t1 >= T.first_output ? 0x80000000u : 0u;
+                for (uint32_t c2 = 0; c2 < 4; ++c2)
+                    d2[(size_t)s * 16 + c1 + 4 * c2] = T.delta[(size_t)t1 * 4 + c2] * 64u | flag;
+            }
+    }
     std::vector<uint32_t> rows(T.delta.size());
     const uint32_t row = T.sigma * 4u;
     for (size_t i = 0; i < rows.size(); ++i) rows[i] = T.delta[i] * row;
@@ -925,7 +1085,8 @@ int upload_dict(ac_dict *d) {
     if (hipMalloc((void **)&d->d_delta, rows.size() * 4) != hipSuccess ||
         hipMalloc((void **)&d->d_out_off, off_bytes) != hipSuccess ||
         hipMalloc((void **)&d->d_out_ids, ids_bytes) != hipSuccess ||
-        hipMalloc((void **)&d->d_hot16, hot16.size() * 2) != hipSuccess) {
+        hipMalloc((void **)&d->d_hot16, hot16.size() * 2) != hipSuccess ||
+        (!d2.empty() && hipMalloc((void **)&d->d_delta2, d2.size() * 4) != hipSuccess)) {
         (void)hipGetLastError();
         release_dict(d);
         return AC_E_NOMEM;
@@ -936,11 +1097,14 @@ int upload_dict(ac_dict *d) {
          hipMemcpy(d->d_out_ids, T.out_ids.data(), T.out_ids.size() * 4, hipMemcpyHostToDevice) !=
              hipSuccess) ||
         hipMemcpy(d->d_hot16, hot16.data(), hot16.size() * 2, hipMemcpyHostToDevice) !=
-            hipSuccess) {
+            hipSuccess ||
+        (!d2.empty() &&
+         hipMemcpy(d->d_delta2, d2.data(), d2.size() * 4, hipMemcpyHostToDevice) != hipSuccess)) {
         (void)hipGetLastError();
         release_dict(d);
         return AC_E_HIP;
     }
+    d->delta2_bytes = (uint32_t)(d2.size() * 4);
     d->device = dev;
     return AC_OK;
 }
@@ -950,8 +1114,10 @@ void release_dict(ac_dict *d) {
     if (d->d_out_off) (void)hipFree(d->d_out_off);
     if (d->d_out_ids) (void)hipFree(d->d_out_ids);
     if (d->d_hot16) (void)hipFree(d->d_hot16);
-    d->d_delta = d->d_out_off = d->d_out_ids = nullptr;
+    if (d->d_delta2) (void)hipFree(d->d_delta2);
+    d->d_delta = d->d_out_off = d->d_out_ids = d->d_delta2 = nullptr;
     d->d_hot16 = nullptr;
+    d->delta2_bytes = 0;
     (void)hipGetLastError();
 }
 
@@ -1066,14 +1232,27 @@ struct Placement {
     uint32_t hot = 0;        // see Inst::hot_bytes
     uint32_t lds_all = 0;
     uint32_t lds_bytes = 0;  // dynamic LDS the count kernel needs
+    uint32_t stride2 = 0;    // two-symbol table in LDS
 };
 
-static Placement choose_placement(const ac_dict *d, uint32_t requested, uint32_t lds_limit) {
+static Placement choose_placement(const ac_dict *d, uint32_t requested, uint32_t lds_limit,
+                                  uint32_t fmt) {
     Placement pl;
     const uint32_t tb = (uint32_t)d->table_bytes;
     const uint32_t sigma = d->host.sigma;
     uint32_t p = requested ? requested : d->placement;
     const bool fits = tb + kLdsPad <= lds_limit;
+    const bool two = fmt == AC_TEXT_2BIT && d->d_delta2 && d->delta2_bytes <= lds_limit;
+    if (p == AC_PLACE_LDS2) {
+        if (two) {
+            pl.stride2 = 1;
+            pl.lds_all = 1;
+            pl.hot = d->delta2_bytes;
+            pl.lds_bytes = d->delta2_bytes;
+            return pl;
+        }
+        p = AC_PLACE_LDS;
+    }
     if (p == AC_PLACE_AUTO) p = fits ? AC_PLACE_LDS : AC_PLACE_HYBRID;
     if (p == AC_PLACE_LDS && !fits) p = AC_PLACE_HYBRID;
     if (p == AC_PLACE_HYBRID && d->hot16_rows == 0) p = AC_PLACE_GLOBAL;
@@ -1124,9 +1303,9 @@ static int resolve_geom(const ac_dict *const *dicts, const uint64_t *ns, uint32_
     // LDS need of the count kernel
     uint32_t lds_bytes = 0;
     const uint32_t req = tune ? tune->placement : 0;
-    if (req > AC_PLACE_HYBRID) return AC_E_INVALID;
+    if (req > AC_PLACE_LDS2) return AC_E_INVALID;
     for (uint32_t i = 0; i < n_inst; ++i)
-        lds_bytes = std::max(lds_bytes, choose_placement(dicts[i], req, lds_limit).lds_bytes);
+        lds_bytes = std::max(lds_bytes, choose_placement(dicts[i], req, lds_limit, fmt).lds_bytes);
     g->lds_bytes = lds_bytes;
     uint32_t bpc = (tune && tune->blocks_per_cu) ? tune->blocks_per_cu
                                                   : std::max(1u, 2048u / g->threads);
@@ -1174,7 +1353,10 @@ static void fill_inst(const ac_dict *d, const void *text, uint64_t n, uint32_t f
     I->table_bytes = (uint32_t)d->table_bytes;
     I->fo_state = d->host.first_output;
     I->fo_bytes = d->host.first_output * d->host.sigma * 4u;
-    const Placement pl = choose_placement(d, req_place, lds_limit);
+    const Placement pl = choose_placement(d, req_place, lds_limit, fmt);
+    I->stride2 = pl.stride2;
+    I->delta2 = d->d_delta2;
+    I->fo2_bytes = d->host.first_output * 64u;
     I->hot_bytes = pl.hot;
     I->lds_all = pl.lds_all;
     I->lds_bytes = pl.lds_bytes;

@@ -22,7 +22,8 @@ import os
 import threading
 from typing import Dict, List, Optional, Sequence
 
-from . import (AC_PLACE_AUTO, AC_PLACE_GLOBAL, AC_PLACE_HYBRID, AC_TEXT_2BIT, ac_device_info,
+from . import (AC_PLACE_AUTO, AC_PLACE_GLOBAL, AC_PLACE_HYBRID, AC_PLACE_LDS2, AC_TEXT_2BIT,
+               ac_device_info,
                ac_scan, ac_scan_batch, ac_scan_workspace_size)
 
 CACHE_ENV = "AC_TUNE_CACHE"
@@ -74,6 +75,8 @@ def candidates(d, n: int, fmt: int) -> List[Optional[dict]]:
     fits = d.info.table_bytes + 1024 <= lds - 512
     chunks = (128, 256, 512) if fmt == AC_TEXT_2BIT else (64, 128, 256)
     places = [AC_PLACE_AUTO] if fits else [AC_PLACE_HYBRID, AC_PLACE_GLOBAL]
+    if fmt == AC_TEXT_2BIT and d.info.sigma == 4 and d.info.states * 64 <= lds - 512:
+        places.append(AC_PLACE_LDS2)
     out: List[Optional[dict]] = [None]  # the library's own choice
     for place in places:
         for chunk in chunks:
@@ -147,8 +150,10 @@ def autotune_batch(items: Sequence[tuple], reps: int = 3, cands: Optional[Sequen
     fmt = items[0][3]
     chunks = (128, 256, 512) if fmt == AC_TEXT_2BIT else (64, 128, 256)
     if cands is None:
-        cands = [None] + [{"chunk": c, "chains": ch, "block_threads": th}
-                          for c in chunks for ch in (1, 2) for th in (512, 1024)]
+        cands = [None] + [{"chunk": c, "chains": ch, "block_threads": th, "placement": pl}
+                          for c in chunks for ch in (1, 2) for th in (512, 1024)
+                          for pl in ((AC_PLACE_AUTO, AC_PLACE_LDS2) if fmt == AC_TEXT_2BIT
+                                     else (AC_PLACE_AUTO,))]
     best, best_ms = None, float("inf")
     for t in cands:
         ms = _time(lambda: ac_scan_batch(items, tune=t, stream=stream), stream, reps)

@@ -49,7 +49,8 @@ def test_batch_mixed_placements_and_empty():
     insts.append(W.Instance(np.zeros(0, dtype=np.uint8), insts[1].patterns, 4, W.DNA))
     dicts, wants, outs, counts, items = _setup(insts, ac.AC_TEXT_2BIT)
     for tune in (None, {"chunk": 64, "block_threads": 256}, {"placement": ac.AC_PLACE_GLOBAL},
-                 {"placement": ac.AC_PLACE_HYBRID, "chunk": 128}):
+                 {"placement": ac.AC_PLACE_HYBRID, "chunk": 128},
+                 {"placement": ac.AC_PLACE_LDS2}, {"placement": ac.AC_PLACE_LDS2, "chains": 4}):
         counts.fill_(-1)
         ac.ac_scan_batch(items, tune=tune)
         torch.cuda.synchronize()

@@ -127,9 +127,13 @@ def test_tiny_corpus(sigma):
         want = oracle.Machine(inst.patterns, sigma).scan_keys(inst.text)
         for fmt in ([ac.AC_TEXT_U8, ac.AC_TEXT_2BIT] if sigma == 4 else [ac.AC_TEXT_U8]):
             t = device_text(inst, fmt)
-            got, total = gpu_keys(d, t, n, fmt, tune={"chunk": 64})
-            assert total == len(want), (seed, fmt)
-            assert np.array_equal(got, want), (seed, fmt)
+            tunes = [{"chunk": 64}]
+            if fmt == ac.AC_TEXT_2BIT:
+                tunes.append({"chunk": 64, "placement": ac.AC_PLACE_LDS2})
+            for tune in tunes:
+                got, total = gpu_keys(d, t, n, fmt, tune=tune)
+                assert total == len(want), (seed, fmt, tune)
+                assert np.array_equal(got, want), (seed, fmt, tune)
 
 
 @pytest.mark.parametrize("fmt", [0, 1])
@@ -158,6 +162,47 @@ def test_launch_shapes_and_placements(place, chunk, threads):
     _say("placement", place, "chunk", chunk, "threads", threads, "states", d.info.states)
     _parity(inst, ac.AC_TEXT_2BIT, tune={"chunk": chunk, "block_threads": threads,
                                          "placement": place}, d=d)
+
+
+def _two_symbol_dict_fits(d):
+    _, lds = ac.ac_device_info()
+    return d.info.states * 64 <= lds - 512
+
+
+@pytest.mark.parametrize("chunk,threads,chains", [(64, 64, 1), (256, 1024, 2), (512, 256, 4),
+                                                  (2048, 1024, 1)])
+def test_two_symbol_stride_dna_small(chunk, threads, chains):
+    inst = W.dna_small()
+    d = ac.ac_build(inst.patterns, sigma=4)
+    assert _two_symbol_dict_fits(d)
+    _parity(inst, ac.AC_TEXT_2BIT, tune={"chunk": chunk, "block_threads": threads,
+                                         "chains": chains, "placement": ac.AC_PLACE_LDS2}, d=d)
+
+
+def test_two_symbol_stride_dense_and_odd_lengths():
+    # poly-A text with A^k for odd and even k: outputs after the first symbol
+    # of a pair (flagged entries) and after the second, in dense segments
+    rng = W.rng_for(41)
+    text = rng.integers(0, 4, size=300_000, dtype=np.uint8)
+    for start in range(1000, 290_000, 9000):
+        text[start:start + int(rng.integers(50, 700))] = 0
+    pats = [np.zeros(k, np.uint8) for k in range(3, 17)]
+    pats += W._cut(rng, text, rng.integers(5, 14, size=120))
+    pats += [rng.integers(0, 4, size=int(L), dtype=np.uint8) for L in rng.integers(5, 14, size=60)]
+    inst = W.Instance(text, W.PatternSet.from_list(pats), 4, W.DNA, "poly_a_odd")
+    d = ac.ac_build(inst.patterns, sigma=4)
+    assert _two_symbol_dict_fits(d)
+    for tune in ({"placement": ac.AC_PLACE_LDS2}, {"placement": ac.AC_PLACE_LDS2, "chunk": 64},
+                 {"placement": ac.AC_PLACE_LDS2, "chains": 4, "chunk": 1024}):
+        _parity(inst, ac.AC_TEXT_2BIT, tune=tune, d=d)
+
+
+def test_two_symbol_stride_falls_back():
+    # tables that do not fit (or byte text) take the single-symbol path
+    inst = W.dna_dense(scale=1 / 512)
+    _parity(inst, ac.AC_TEXT_2BIT, tune={"placement": ac.AC_PLACE_LDS2})
+    small = W.dna_small(scale=1 / 8)
+    _parity(small, ac.AC_TEXT_U8, tune={"placement": ac.AC_PLACE_LDS2})
 
 
 @pytest.mark.parametrize("place", [ac.AC_PLACE_LDS, ac.AC_PLACE_GLOBAL, ac.AC_PLACE_HYBRID])
