@@ -23,8 +23,7 @@ import threading
 from typing import Dict, List, Optional, Sequence
 
 from . import (AC_PLACE_AUTO, AC_PLACE_GLOBAL, AC_PLACE_HYBRID, AC_PLACE_LDS2, AC_TEXT_2BIT,
-               ac_device_info,
-               ac_scan, ac_scan_batch, ac_scan_workspace_size)
+               ac_device_info, ac_scan, ac_scan_batch, ac_scan_workspace_size)
 
 CACHE_ENV = "AC_TUNE_CACHE"
 _lock = threading.Lock()
