@@ -259,6 +259,9 @@ def main():
     if not args.no_batch:
         result["batched"] = bench_batch(args, torch, ac, W, dev, stream)
 
+    # --------------------------------------------------------- build vs scan
+    result["build_vs_scan"] = bench_build(args, ac, W, inst, step_ms)
+
     # --------------------------------------------------------- serving
     if not args.no_serve:
         result["serve"] = bench_serve(args, torch, ac, W)
@@ -346,6 +349,25 @@ def bench_batch(args, torch, ac, W, dev, stream):
             "speedup_batched_vs_plain": round(plain_ms / batch_ms, 2),
             "speedup_graph_vs_plain": round(plain_ms / graph_ms, 2),
             "identical_to_plain": bool(same and same_graph)}
+
+
+def bench_build(args, ac, W, inst, step_ms):
+    """Host build time (stage 1) against scan time (stage 2): the paper finds
+    machine construction dominating on its CPUs.  Parallel (level by level,
+    up to 16 threads) and one-thread builds of the same tables."""
+    rows = []
+    sets = [("dna_dense", inst.patterns)] + [
+        (f"serve dictionary {k}", p) for k, p in enumerate(W.serve(requests=1).dictionaries)]
+    for name, pats in sets:
+        par = min(ac.ac_build(pats, sigma=4, host_only=True).info.build_ms for _ in range(2))
+        ser = min(ac.ac_build(pats, sigma=4, host_only=True, serial=True).info.build_ms
+                  for _ in range(2))
+        d = ac.ac_build(pats, sigma=4, host_only=True)
+        rows.append({"dictionary": name, "patterns": int(pats.count), "states": d.info.states,
+                     "build_ms": round(par, 2), "build_ms_one_thread": round(ser, 2)})
+    log("[bench] build: " + ", ".join(f"{r['dictionary']} {r['build_ms']} ms" for r in rows))
+    return {"dictionaries": rows, "dna_dense_step_ms": round(step_ms, 4),
+            "dna_dense_build_over_step": round(rows[0]["build_ms"] / step_ms, 2)}
 
 
 def bench_serve(args, torch, ac, W):

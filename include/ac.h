@@ -73,6 +73,8 @@ extern "C" {
                              * bytes of LDS, else falls back to AC_PLACE_LDS */
 
 #define AC_BUILD_HOST_ONLY 1u /* compile tables on the host only (no GPU)   */
+#define AC_BUILD_SERIAL 2u    /* compile on one host thread (default: up to 16
+                               * threads, level by level); same tables      */
 
 /* Work units of the scan: a segment is AC_SEGMENT text symbols; segments
  * with at least AC_DENSE_SEGMENT_MATCHES matches are written by a whole
@@ -92,7 +94,7 @@ typedef struct {
 typedef struct {
     uint32_t sigma;      /* alphabet size, 2..256                            */
     uint32_t placement;  /* AC_PLACE_* default for scans with this dict      */
-    uint32_t flags;      /* AC_BUILD_HOST_ONLY or 0                          */
+    uint32_t flags;      /* AC_BUILD_HOST_ONLY | AC_BUILD_SERIAL, or 0       */
     uint32_t hot_states; /* rows kept in LDS by AC_PLACE_HYBRID; 0 = fill LDS */
 } ac_build_opts;
 

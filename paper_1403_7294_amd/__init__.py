@@ -41,6 +41,7 @@ AC_ALPHA_DNA = 0
 AC_ALPHA_PROTEIN = 1
 AC_PLACE_AUTO, AC_PLACE_LDS, AC_PLACE_GLOBAL, AC_PLACE_HYBRID, AC_PLACE_LDS2 = 0, 1, 2, 3, 4
 AC_BUILD_HOST_ONLY = 1
+AC_BUILD_SERIAL = 2
 AC_SEGMENT = 64
 AC_DENSE_SEGMENT_MATCHES = 256
 
@@ -202,10 +203,11 @@ def _csr(patterns) -> Tuple[np.ndarray, np.ndarray]:
 # ------------------------------------------------------------------ ABI calls
 
 def ac_build(patterns, sigma: int = 4, placement: int = AC_PLACE_AUTO, host_only: bool = False,
-             hot_states: int = 0) -> "Dict":
+             hot_states: int = 0, serial: bool = False) -> "Dict":
     """Stage 1: compile patterns (paper section III.A) into a dictionary."""
     sym, off = _csr(patterns)
-    opts = ac_build_opts(sigma, placement, AC_BUILD_HOST_ONLY if host_only else 0, hot_states)
+    flags = (AC_BUILD_HOST_ONLY if host_only else 0) | (AC_BUILD_SERIAL if serial else 0)
+    opts = ac_build_opts(sigma, placement, flags, hot_states)
     h = ctypes.c_void_p()
     _check(lib().ac_build(sym.ctypes.data, off.ctypes.data, len(off) - 1, ctypes.byref(opts),
                           ctypes.byref(h)), "ac_build")

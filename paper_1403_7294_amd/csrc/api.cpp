@@ -16,13 +16,15 @@ int ac_build(const uint8_t *symbols, const uint64_t *offsets, uint32_t n_pattern
     *out = nullptr;
     ac_build_opts o = {4, AC_PLACE_AUTO, 0, 0};
     if (opts) o = *opts;
-    if (o.placement > AC_PLACE_LDS2 || (o.flags & ~AC_BUILD_HOST_ONLY)) return AC_E_INVALID;
+    if (o.placement > AC_PLACE_LDS2 || (o.flags & ~(AC_BUILD_HOST_ONLY | AC_BUILD_SERIAL)))
+        return AC_E_INVALID;
     ac_dict *d = new (std::nothrow) ac_dict();
     if (!d) return AC_E_NOMEM;
     const auto t0 = std::chrono::steady_clock::now();
     int rc;
     try {
-        rc = acx::compile_automaton(symbols, offsets, n_patterns, o.sigma, &d->host);
+        rc = acx::compile_automaton(symbols, offsets, n_patterns, o.sigma, &d->host,
+                                    (o.flags & AC_BUILD_SERIAL) ? 1u : 0u);
     } catch (const std::bad_alloc &) {
         rc = AC_E_NOMEM;
     }

@@ -14,10 +14,10 @@ namespace acx {
 // Host form of a compiled dictionary.
 //
 // States are renumbered so that the root is 0, states whose output set is
-// empty come first in breadth-first order (shallow, frequently visited rows
-// first, which is what the LDS-resident "hot" prefix of the table wants), and
-// states with a non-empty output set come last: "state >= first_output" is
-// then the whole match test of the scan.
+// empty come first, most likely to be visited first (which is what the
+// LDS-resident "hot" prefix of the table wants), and states with a non-empty
+// output set come last: "state >= first_output" is then the whole match test
+// of the scan.
 struct HostTables {
     uint32_t sigma = 0;
     uint32_t states = 0;
@@ -32,9 +32,10 @@ struct HostTables {
 };
 
 // Stage 1 of the method on the host: trie, failure links, completed
-// transitions, output sets, renumbering.  Returns an AC_* status.
+// transitions, output sets, renumbering, on `threads` host threads (0: up to
+// 16).  The tables do not depend on the thread count.  Returns an AC_* status.
 int compile_automaton(const uint8_t *symbols, const uint64_t *offsets, uint32_t n_patterns,
-                      uint32_t sigma, HostTables *out);
+                      uint32_t sigma, HostTables *out, uint32_t threads = 0);
 
 // Exact division of a row byte offset (state * sigma * 4) by sigma * 4:
 // state = (offset >> tz) * inv (mod 2^32), with sigma*4 = 2^tz * odd and

@@ -144,3 +144,36 @@ def test_info_struct_layout():
     assert ctypes.sizeof(ac.ac_build_opts) == 16
     assert ctypes.sizeof(ac.ac_tune) == 20
     assert ctypes.sizeof(ac.ac_batch_item) == 56
+
+
+@pytest.mark.parametrize("which", ["tiny", "dna_dense", "protein", "serve_large"])
+def test_parallel_build_equals_serial(which):
+    """The level-parallel host build gives exactly the serial build's tables
+    (the serve dictionary has more than 65,536 output-free states, so the
+    partial ranking path is taken too)."""
+    if which == "tiny":
+        pats, sigma = W.tiny(77, 4, max_pats=12).patterns, 4
+    elif which == "dna_dense":
+        pats, sigma = W.dna_dense(scale=1 / 4096).patterns, 4
+    elif which == "protein":
+        pats, sigma = W.protein(scale=1 / 64).patterns, 20
+    else:
+        pats, sigma = W.serve(requests=1).dictionaries[5], 4
+    a = ac.ac_build(pats, sigma=sigma, host_only=True, serial=True)
+    b = ac.ac_build(pats, sigma=sigma, host_only=True)
+    for x, y in zip(ac.ac_debug_export(a), ac.ac_debug_export(b)):
+        assert np.array_equal(x, y)
+    assert a.info.states == b.info.states and a.info.first_output_state == b.info.first_output_state
+    if which == "serve_large":
+        assert a.info.first_output_state > 65536
+        # the scan behaviour is the oracle's on a sample text
+        rng = W.rng_for(9)
+        text = rng.integers(0, 4, size=20000, dtype=np.uint8)
+        sub = W.PatternSet.from_list(W._cut(rng, text, rng.integers(10, 31, size=50)) +
+                                     pats.as_list()[:2000])
+        c = ac.ac_build(sub, sigma=4, host_only=True)
+        delta, out_off, out_ids, depth = ac.ac_debug_export(c)
+        want = oracle.Machine(sub, 4).scan_keys(text)
+        got = emulate_scan(delta, out_off, out_ids, c.info.first_output_state, text, 1024,
+                           c.info.max_len - 1)
+        assert np.array_equal(got, want)
