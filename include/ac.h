@@ -187,6 +187,50 @@ int ac_scan(const ac_dict *dict, const void *d_text, uint64_t n, uint32_t fmt,
             const ac_tune *tune, void *d_workspace, uint64_t workspace_bytes,
             void *stream);
 
+/* ---------------------------------------------------------------- variants
+ * ac_build_partitioned: the paper's second design (section IV.A, Figure 3):
+ * the pattern list is split into `parts` contiguous slices of about equal
+ * length, and each slice is compiled into its own machine; parts = 0 picks
+ * the fewest slices whose tables all fit LDS (as 16-bit rows).  Pattern ids
+ * stay global (slice i reports ids from its first pattern's index).  The
+ * result is used with ac_scan like any dictionary: every machine scans the
+ * whole text (one batched launch sequence), and the slices' matches are
+ * merged into (end_pos, pattern_id) order by a stable radix sort on end
+ * position.  Such a scan synchronises its stream once to size temporary
+ * buffers, takes them from HIP's stream-ordered allocator, and ignores
+ * d_workspace (ac_scan_workspace_size, ac_debug_export and the batch entry
+ * points reject a partitioned dictionary: AC_E_INVALID).  Errors as for
+ * ac_build. */
+int ac_build_partitioned(const uint8_t *symbols, const uint64_t *offsets, uint32_t n_patterns,
+                         const ac_build_opts *opts, uint32_t parts, ac_dict **out);
+/* Number of slices of a partitioned dictionary (0 for an ordinary one) and,
+ * if first_ids is not NULL, the first pattern id of each (parts entries). */
+int ac_dict_parts(const ac_dict *dict, uint32_t *parts, uint32_t *first_ids);
+
+/* ac_scan_pfac: the failure-less form of stage 2 (related work, section
+ * II): one thread per text position walks the trie (goto function only)
+ * from the root along the text until an edge is missing and reports the
+ * patterns ending exactly at each state it enters, so every occurrence is
+ * found from its start; up to max_len lookups per position instead of one.
+ * Arguments and results as for ac_scan (the same set, in (end_pos,
+ * pattern_id) order after a radix sort); n < 2^31.  Synchronises the stream
+ * once to size temporary buffers, which come from HIP's stream-ordered
+ * allocator.  AC_E_TOO_LARGE if the table has 2^31 bytes or more. */
+int ac_scan_pfac(const ac_dict *dict, const void *d_text, uint64_t n, uint32_t fmt,
+                 ac_match *d_out, uint64_t capacity, uint64_t *d_count, void *stream);
+
+/* ac_sort_matches: sort n device records in place into (end_pos,
+ * pattern_id) order -- the order ac_scan writes -- by a radix sort over the
+ * low end_bits bits of end_pos (0 = 32) and all of pattern_id.  With
+ * AC_SORT_BY_END only end_pos is sorted on, stably: enough when records with
+ * equal end_pos are already in id order.  n < 2^31.  d_workspace of
+ * ac_sort_workspace_size(n) bytes, or NULL to take it from HIP's
+ * stream-ordered allocator.  Stream-ordered. */
+#define AC_SORT_BY_END 1u
+int ac_sort_workspace_size(uint64_t n, uint64_t *bytes);
+int ac_sort_matches(ac_match *d_matches, uint64_t n, uint32_t flags, uint32_t end_bits,
+                    void *d_workspace, uint64_t workspace_bytes, void *stream);
+
 /* ---------------------------------------------------------------- batches
  * One instance of a batch: its own dictionary, text, output and count,
  * with the meaning of the same-named ac_scan arguments. */
@@ -230,7 +274,9 @@ int ac_scan_batch(const ac_batch_item *items, uint32_t n_items, const ac_tune *t
 #define AC_K_EMIT 4     /* pass 2, sparse segments: one lane each          */
 #define AC_K_TOTALS 5   /* per-instance totals (batches)                 */
 #define AC_K_EMIT_DENSE 6 /* pass 2, dense segments: one wave each       */
-#define AC_K_KINDS 7
+#define AC_K_PFAC 7     /* failure-less scan (count and write passes)     */
+#define AC_K_SORT 8     /* radix sort of match records                    */
+#define AC_K_KINDS 9
 int ac_timing_enable(int on);
 int ac_timing_read(double *ms, uint64_t *launches, int reset);
 

@@ -50,12 +50,15 @@ ABI_SYMBOLS = [
     "ac_build", "ac_destroy", "ac_dict_get_info", "ac_debug_export", "ac_encode",
     "ac_scan_workspace_size", "ac_scan", "ac_batch_create", "ac_batch_run",
     "ac_batch_destroy", "ac_scan_batch", "ac_status_str", "ac_device_info",
-    "ac_timing_enable", "ac_timing_read",
+    "ac_timing_enable", "ac_timing_read", "ac_build_partitioned", "ac_dict_parts",
+    "ac_scan_pfac", "ac_sort_workspace_size", "ac_sort_matches",
 ]
-AC_K_ENCODE, AC_K_COUNT, AC_K_OFFSETS, AC_K_SCATTER, AC_K_EMIT, AC_K_TOTALS, AC_K_EMIT_DENSE = \
-    range(7)
-AC_K_KINDS = 7
-KERNEL_NAMES = ["encode", "count", "offsets", "scatter", "emit", "totals", "emit_dense"]
+AC_SORT_BY_END = 1
+(AC_K_ENCODE, AC_K_COUNT, AC_K_OFFSETS, AC_K_SCATTER, AC_K_EMIT, AC_K_TOTALS, AC_K_EMIT_DENSE,
+ AC_K_PFAC, AC_K_SORT) = range(9)
+AC_K_KINDS = 9
+KERNEL_NAMES = ["encode", "count", "offsets", "scatter", "emit", "totals", "emit_dense", "pfac",
+                "sort"]
 
 
 class LibraryMissing(RuntimeError):
@@ -146,6 +149,17 @@ def lib():
     L.ac_timing_enable.restype = i
     L.ac_timing_read.argtypes = [P, P, i]
     L.ac_timing_read.restype = i
+    L.ac_build_partitioned.argtypes = [P, P, u32, ctypes.POINTER(ac_build_opts), u32,
+                                       ctypes.POINTER(P)]
+    L.ac_build_partitioned.restype = i
+    L.ac_dict_parts.argtypes = [P, ctypes.POINTER(u32), P]
+    L.ac_dict_parts.restype = i
+    L.ac_scan_pfac.argtypes = [P, P, u64, u32, P, u64, P, P]
+    L.ac_scan_pfac.restype = i
+    L.ac_sort_workspace_size.argtypes = [u64, ctypes.POINTER(u64)]
+    L.ac_sort_workspace_size.restype = i
+    L.ac_sort_matches.argtypes = [P, u64, u32, u32, P, u64, P]
+    L.ac_sort_matches.restype = i
     _lib = L
     return L
 
@@ -212,6 +226,51 @@ def ac_build(patterns, sigma: int = 4, placement: int = AC_PLACE_AUTO, host_only
     _check(lib().ac_build(sym.ctypes.data, off.ctypes.data, len(off) - 1, ctypes.byref(opts),
                           ctypes.byref(h)), "ac_build")
     return Dict(h)
+
+
+def ac_build_partitioned(patterns, sigma: int = 4, parts: int = 0, placement: int = AC_PLACE_AUTO,
+                         host_only: bool = False) -> "Dict":
+    """The paper's second design: one machine per contiguous pattern slice
+    (parts = 0: the fewest slices whose tables fit LDS)."""
+    sym, off = _csr(patterns)
+    opts = ac_build_opts(sigma, placement, AC_BUILD_HOST_ONLY if host_only else 0, 0)
+    h = ctypes.c_void_p()
+    _check(lib().ac_build_partitioned(sym.ctypes.data, off.ctypes.data, len(off) - 1,
+                                      ctypes.byref(opts), parts, ctypes.byref(h)),
+           "ac_build_partitioned")
+    return Dict(h)
+
+
+def ac_dict_parts(d: "Dict") -> List[int]:
+    """First pattern id of each slice ([] for an ordinary dictionary)."""
+    k = ctypes.c_uint32()
+    _check(lib().ac_dict_parts(d.handle, ctypes.byref(k), None), "ac_dict_parts")
+    ids = (ctypes.c_uint32 * max(1, k.value))()
+    _check(lib().ac_dict_parts(d.handle, ctypes.byref(k), ids), "ac_dict_parts")
+    return list(ids[:k.value])
+
+
+def ac_scan_pfac(d: "Dict", text_dev, n: int, fmt: int, out_dev, capacity: int, count_dev,
+                 stream=None) -> None:
+    """Failure-less scan (one thread per start position); same results as ac_scan."""
+    _check(lib().ac_scan_pfac(d.handle, text_dev.data_ptr() if n else None, n, fmt,
+                              out_dev.data_ptr() if capacity else None, capacity,
+                              count_dev.data_ptr(), _stream_ptr(stream)), "ac_scan_pfac")
+
+
+def ac_sort_workspace_size(n: int) -> int:
+    b = ctypes.c_uint64()
+    _check(lib().ac_sort_workspace_size(n, ctypes.byref(b)), "ac_sort_workspace_size")
+    return b.value
+
+
+def ac_sort_matches(matches_dev, n: int, flags: int = 0, end_bits: int = 0, workspace_dev=None,
+                    stream=None) -> None:
+    """Sort (M, 2) int32 match records in place into (end, id) order."""
+    ws = workspace_dev.data_ptr() if workspace_dev is not None else None
+    wsb = workspace_dev.numel() * workspace_dev.element_size() if workspace_dev is not None else 0
+    _check(lib().ac_sort_matches(matches_dev.data_ptr() if n else None, n, flags, end_bits, ws,
+                                 wsb, _stream_ptr(stream)), "ac_sort_matches")
 
 
 def ac_destroy(d: "Dict") -> None:

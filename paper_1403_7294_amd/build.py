@@ -23,7 +23,7 @@ HIPCC = shutil.which("hipcc") or os.path.join(ROCM, "bin", "hipcc")
 ARCH = "gfx950"
 
 HOST_SOURCES = ["automaton.cpp", "api.cpp"]
-HIP_SOURCES = ["scan.hip"]
+HIP_SOURCES = ["scan.hip", "sort.hip"]
 DEPS = ["internal.h", "batch.inc", "device_common.h"]
 
 # packed fp32 instructions are disabled on every HIP compile (they are never

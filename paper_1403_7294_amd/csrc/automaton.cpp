@@ -297,8 +297,6 @@ int compile_automaton(const uint8_t *symbols, const uint64_t *offsets, uint32_t 
             }
         });
     }
-    child.clear();
-    child.shrink_to_fit();
     // output-free states as (log-probability, breadth-first position); the
     // most likely come first, ties in breadth-first order (the root, with
     // log-probability 0, is first)
@@ -355,6 +353,25 @@ int compile_automaton(const uint8_t *symbols, const uint64_t *offsets, uint32_t 
                 T.delta[k * sigma + a] = new_id[delta[(size_t)s * sigma + a]];
         }
     });
+    // the trie alone and each state's own patterns, renumbered
+    T.go.assign((size_t)S * sigma, 0);
+    T.own_off.assign(S + 1, 0);
+    for (uint32_t k = 0; k < S; ++k)
+        T.own_off[k + 1] = T.own_off[k] + (own_cnt[order[k] + 1] - own_cnt[order[k]]);
+    T.own_ids.assign(n_patterns, 0);
+    parallel_for(threads, S, [&](size_t k0, size_t k1) {
+        for (size_t k = k0; k < k1; ++k) {
+            const uint32_t s = order[k];
+            for (uint32_t a = 0; a < sigma; ++a) {
+                const int32_t t = child[(size_t)s * sigma + a];
+                T.go[k * sigma + a] = t < 0 ? 0u : new_id[t];
+            }
+            std::copy(own_ids.begin() + own_cnt[s], own_ids.begin() + own_cnt[s + 1],
+                      T.own_ids.begin() + T.own_off[k]);
+        }
+    });
+    child.clear();
+    child.shrink_to_fit();
     const uint32_t n_out = S - first_output;
     T.out_off.assign(n_out + 1, 0);
     T.max_output = 0;

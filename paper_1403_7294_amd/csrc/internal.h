@@ -29,6 +29,12 @@ struct HostTables {
     std::vector<uint32_t> out_off;  // states-first_output+1
     std::vector<uint32_t> out_ids;  // concatenated output sets, ids ascending
     std::vector<uint32_t> depth;    // prefix length spelled by each state
+    // goto function alone (the trie), for the failure-less kernel:
+    // states*sigma child ids, 0 = no edge (the root is nobody's child), and
+    // the patterns ending exactly at each state (CSR over all states)
+    std::vector<uint32_t> go;
+    std::vector<uint32_t> own_off;  // states+1
+    std::vector<uint32_t> own_ids;  // patterns, ids ascending per state
 };
 
 // Stage 1 of the method on the host: trie, failure links, completed
@@ -48,6 +54,8 @@ RowDiv make_row_div(uint32_t sigma);
 
 }  // namespace acx
 
+struct ihipStream_t;
+
 // The opaque dictionary handle.
 struct ac_dict {
     acx::HostTables host;
@@ -66,6 +74,15 @@ struct ac_dict {
     // when the state after the first symbol has an output set
     uint32_t *d_delta2 = nullptr;
     uint32_t delta2_bytes = 0;
+    // failure-less kernel tables: goto entries as row offsets of the child
+    // (0 = no edge), bit 31 set when the child has patterns of its own
+    uint32_t *d_go = nullptr;
+    uint32_t *d_own_off = nullptr;
+    uint32_t *d_own_ids = nullptr;
+    // a partitioned dictionary (pattern slices, each its own machine) holds
+    // no tables itself; part i reports pattern ids from part_base[i]
+    std::vector<ac_dict *> parts;
+    std::vector<uint32_t> part_base;
     uint64_t table_bytes = 0;
 };
 
@@ -75,4 +92,13 @@ int upload_dict(ac_dict *d);
 void release_dict(ac_dict *d);
 // Largest dynamic LDS allocation one block may use, and compute units.
 int device_limits(uint32_t *cus, uint32_t *lds_bytes);
+// Radix sort of match records into (end, id) order (sort.hip).
+uint64_t sort_workspace_bytes(uint64_t n);
+int sort_matches(ac_match *d, uint64_t n, uint32_t flags, uint32_t end_bits, void *ws,
+                 uint64_t ws_bytes, ihipStream_t *st);
+int exclusive_sum_u64(const unsigned long long *in, unsigned long long *out, uint64_t n,
+                      ihipStream_t *st);
+// Scan with a partitioned dictionary (scan.hip).
+int scan_partitioned(const ac_dict *d, const void *text, uint64_t n, uint32_t fmt, ac_match *out,
+                     uint64_t cap, uint64_t *count, const ac_tune *tune, ihipStream_t *st);
 }  // namespace acx

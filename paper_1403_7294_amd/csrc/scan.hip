@@ -1080,13 +1080,26 @@ int upload_dict(ac_dict *d) {
     std::vector<uint32_t> rows(T.delta.size());
     const uint32_t row = T.sigma * 4u;
     for (size_t i = 0; i < rows.size(); ++i) rows[i] = T.delta[i] * row;
+    // failure-less kernel: child row offsets (bit 31: the child has its own
+    // patterns); row offsets must stay below 2^31
+    std::vector<uint32_t> go;
+    if (rows.size() * 4 < (1ull << 31)) {
+        go.resize(T.go.size());
+        for (size_t i = 0; i < go.size(); ++i) {
+            const uint32_t t = T.go[i];
+            go[i] = t ? t * row | (T.own_off[t + 1] > T.own_off[t] ? 0x80000000u : 0u) : 0u;
+        }
+    }
     const size_t off_bytes = T.out_off.size() * 4;
     const size_t ids_bytes = std::max<size_t>(4, T.out_ids.size() * 4);
     if (hipMalloc((void **)&d->d_delta, rows.size() * 4) != hipSuccess ||
         hipMalloc((void **)&d->d_out_off, off_bytes) != hipSuccess ||
         hipMalloc((void **)&d->d_out_ids, ids_bytes) != hipSuccess ||
         hipMalloc((void **)&d->d_hot16, hot16.size() * 2) != hipSuccess ||
-        (!d2.empty() && hipMalloc((void **)&d->d_delta2, d2.size() * 4) != hipSuccess)) {
+        (!d2.empty() && hipMalloc((void **)&d->d_delta2, d2.size() * 4) != hipSuccess) ||
+        (!go.empty() && (hipMalloc((void **)&d->d_go, go.size() * 4) != hipSuccess ||
+                         hipMalloc((void **)&d->d_own_off, T.own_off.size() * 4) != hipSuccess ||
+                         hipMalloc((void **)&d->d_own_ids, T.own_ids.size() * 4) != hipSuccess))) {
         (void)hipGetLastError();
         release_dict(d);
         return AC_E_NOMEM;
@@ -1099,7 +1112,13 @@ int upload_dict(ac_dict *d) {
         hipMemcpy(d->d_hot16, hot16.data(), hot16.size() * 2, hipMemcpyHostToDevice) !=
             hipSuccess ||
         (!d2.empty() &&
-         hipMemcpy(d->d_delta2, d2.data(), d2.size() * 4, hipMemcpyHostToDevice) != hipSuccess)) {
+         hipMemcpy(d->d_delta2, d2.data(), d2.size() * 4, hipMemcpyHostToDevice) != hipSuccess) ||
+        (!go.empty() &&
+         (hipMemcpy(d->d_go, go.data(), go.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(d->d_own_off, T.own_off.data(), T.own_off.size() * 4,
+                    hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(d->d_own_ids, T.own_ids.data(), T.own_ids.size() * 4,
+                    hipMemcpyHostToDevice) != hipSuccess))) {
         (void)hipGetLastError();
         release_dict(d);
         return AC_E_HIP;
@@ -1115,7 +1134,11 @@ void release_dict(ac_dict *d) {
     if (d->d_out_ids) (void)hipFree(d->d_out_ids);
     if (d->d_hot16) (void)hipFree(d->d_hot16);
     if (d->d_delta2) (void)hipFree(d->d_delta2);
+    if (d->d_go) (void)hipFree(d->d_go);
+    if (d->d_own_off) (void)hipFree(d->d_own_off);
+    if (d->d_own_ids) (void)hipFree(d->d_own_ids);
     d->d_delta = d->d_out_off = d->d_out_ids = d->d_delta2 = nullptr;
+    d->d_go = d->d_own_off = d->d_own_ids = nullptr;
     d->d_hot16 = nullptr;
     d->delta2_bytes = 0;
     (void)hipGetLastError();
@@ -1496,7 +1519,7 @@ int ac_timing_read(double *ms, uint64_t *launches, int reset) {
 
 int ac_scan_workspace_size(const ac_dict *d, uint64_t n, uint32_t fmt, const ac_tune *tune,
                            uint64_t *bytes) {
-    if (!d || !bytes) return AC_E_INVALID;
+    if (!d || !bytes || !d->parts.empty()) return AC_E_INVALID;
     int rc = validate_text(d, (const void *)1, n, fmt);
     if (rc) return rc;
     Geom g;
@@ -1510,8 +1533,11 @@ int ac_scan(const ac_dict *d, const void *d_text, uint64_t n, uint32_t fmt, ac_m
             uint64_t capacity, uint64_t *d_count, const ac_tune *tune, void *d_workspace,
             uint64_t workspace_bytes, void *stream) {
     if (!d || !d_count) return AC_E_INVALID;
-    if (!d->d_delta) return AC_E_NO_DEVICE;
     if (capacity && !d_out) return AC_E_INVALID;
+    if (!d->parts.empty())
+        return scan_partitioned(d, d_text, n, fmt, d_out, capacity, d_count, tune,
+                                (hipStream_t)stream);
+    if (!d->d_delta) return AC_E_NO_DEVICE;
     int rc = validate_text(d, d_text, n, fmt);
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
@@ -1583,3 +1609,4 @@ int ac_encode(const uint8_t *d_ascii, uint64_t n, uint32_t alphabet, uint32_t fm
 }  // extern "C"
 
 #include "batch.inc"
+#include "extra.inc"

@@ -177,3 +177,19 @@ def test_parallel_build_equals_serial(which):
         got = emulate_scan(delta, out_off, out_ids, c.info.first_output_state, text, 1024,
                            c.info.max_len - 1)
         assert np.array_equal(got, want)
+
+
+def test_partitioned_build_host():
+    """Slices are contiguous, start at pattern 0, and each slice's table fits
+    LDS as 16-bit rows when the count is chosen automatically."""
+    pats = W.dna_dense(scale=1 / 4096).patterns
+    d = ac.ac_build_partitioned(pats, sigma=4, host_only=True)
+    bases = ac.ac_dict_parts(d)
+    assert bases[0] == 0 and all(a < b for a, b in zip(bases, bases[1:]))
+    assert len(bases) >= 2
+    assert d.info.patterns == pats.count
+    with pytest.raises(ac.ACError):
+        ac.ac_debug_export(d)
+    d3 = ac.ac_build_partitioned(pats, sigma=4, parts=3, host_only=True)
+    assert len(ac.ac_dict_parts(d3)) == 3
+    assert ac.ac_dict_parts(ac.ac_build(pats, sigma=4, host_only=True)) == []
