@@ -68,6 +68,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the partitioned / failure-less / two-symbol comparisons")
     ap.add_argument("--serve-requests", type=int, default=10_000,
                     help="requests timed at the fixed arrival rate")
     ap.add_argument("--scale", type=float, default=1.0, help="shrink the workload (testing)")
@@ -259,6 +261,11 @@ def main():
     if not args.no_batch:
         result["batched"] = bench_batch(args, torch, ac, W, dev, stream)
 
+    # --------------------------------------------------------- variants
+    if not args.no_variants:
+        result["variants"] = bench_variants(args, torch, ac, W, inst, d, packed, out, total,
+                                            scan_ms)
+
     # --------------------------------------------------------- build vs scan
     result["build_vs_scan"] = bench_build(args, ac, W, inst, step_ms)
 
@@ -336,6 +343,13 @@ def bench_batch(args, torch, ac, W, dev, stream):
     graph_ms = timeit(g.replay, reps)
     same_graph = all(np.array_equal(ac.match_keys(o[:int(c)]), k)
                      for o, c, k in zip(outs, caps, plain_keys))
+    # the same batch with the two-symbol table where it fits LDS
+    two = {"placement": ac.AC_PLACE_LDS2, "chains": 1}
+    plan2 = ac.ac_batch_create(items, tune=two)
+    two_ms = timeit(lambda: ac.ac_batch_run(plan2), reps)
+    plan2.close()
+    same_two = all(np.array_equal(ac.match_keys(o[:int(c)]), k)
+                   for o, c, k in zip(outs, caps, plain_keys))
     log(f"[bench] batch: plain {plain_ms:.3f} ms, batched {batch_ms:.3f} ms, "
         f"graph {graph_ms:.3f} ms, identical {same and same_graph}")
     plan.close()
@@ -348,7 +362,62 @@ def bench_batch(args, torch, ac, W, dev, stream):
             "batched_gbases_s": round(bases / (batch_ms * 1e-3) / 1e9, 3),
             "speedup_batched_vs_plain": round(plain_ms / batch_ms, 2),
             "speedup_graph_vs_plain": round(plain_ms / graph_ms, 2),
-            "identical_to_plain": bool(same and same_graph)}
+            "two_symbol_batched_ms": round(two_ms, 3),
+            "identical_to_plain": bool(same and same_graph and same_two)}
+
+
+def _timed(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t) / reps * 1e3
+
+
+def bench_variants(args, torch, ac, W, inst, d, packed, out, total, scan_ms):
+    """The other forms of stage 2 on the same workloads, each checked equal to
+    the main scan's output: the paper's second design (one machine per
+    pattern slice, each table in LDS, merged by a stable sort), the
+    failure-less kernel (one thread per start position, then a sort), and the
+    two-symbol table on an LDS-resident dictionary.  Wall-clock per call
+    (the partitioned and failure-less forms synchronise once per call)."""
+    fmt = ac.AC_TEXT_2BIT
+    n = len(inst.text)
+    res = {"dna_dense_scan_ms": round(scan_ms, 4)}
+    out2 = torch.empty_like(out)
+    cnt = torch.zeros(1, dtype=torch.int64, device=out.device)
+    part = ac.ac_build_partitioned(inst.patterns, sigma=4)
+    ms = _timed(torch, lambda: ac.ac_scan(part, packed, n, fmt, out2, total, cnt), 3)
+    res["partitioned"] = {"parts": len(ac.ac_dict_parts(part)), "ms": round(ms, 3),
+                          "identical": bool(torch.equal(out2, out))}
+    part.close()
+    out2.fill_(0)
+    ms = _timed(torch, lambda: ac.ac_scan_pfac(d, packed, n, fmt, out2, total, cnt), 3)
+    res["failure_less"] = {"ms": round(ms, 3), "identical": bool(torch.equal(out2, out))}
+    del out2
+    # an LDS-resident dictionary (dna_small) over its own 1 Mi-base text
+    sm = W.dna_small()
+    ds = ac.ac_build(sm.patterns, sigma=4)
+    letters = torch.from_numpy(W.to_ascii(sm.text, W.DNA)).to(out.device)
+    ps = torch.empty((len(sm.text) + 3) // 4, dtype=torch.uint8, device=out.device)
+    ac.ac_encode(letters, ac.AC_ALPHA_DNA, fmt, ps)
+    ref, tot = ac.scan(ds, ps, fmt, n=len(sm.text))
+    o = torch.empty_like(ref)
+    small = {}
+    for name, fn in [
+            ("lds", lambda: ac.ac_scan(ds, ps, len(sm.text), fmt, o, tot, cnt)),
+            ("lds_two_symbol", lambda: ac.ac_scan(ds, ps, len(sm.text), fmt, o, tot, cnt,
+                                                  tune={"placement": ac.AC_PLACE_LDS2})),
+            ("failure_less", lambda: ac.ac_scan_pfac(ds, ps, len(sm.text), fmt, o, tot, cnt))]:
+        ms = _timed(torch, fn, 20)
+        small[name] = {"ms": round(ms, 4), "identical": bool(torch.equal(o, ref))}
+    res["dna_small"] = small
+    log("[bench] variants: partitioned %(p)s ms (%(k)d parts), failure-less %(f)s ms; dna_small %(s)s"
+        % {"p": res["partitioned"]["ms"], "k": res["partitioned"]["parts"],
+           "f": res["failure_less"]["ms"], "s": {k: v["ms"] for k, v in small.items()}})
+    return res
 
 
 def bench_build(args, ac, W, inst, step_ms):
