@@ -45,6 +45,14 @@ namespace acx {
 
 constexpr uint32_t kSeg = AC_SEGMENT;     // symbols per segment
 constexpr uint32_t kQuarter = kSeg / 4;   // symbols per quarter segment
+// Output events of a segment kept by the count pass (at most 4): output
+// set index << 6 | position in the segment; unused slots kEvNone, and
+// kEvMany in the first slot when the segment has more (or an index that
+// does not fit 26 bits).
+constexpr uint32_t kEvSlots = 4;
+constexpr uint32_t kEvNone = 0xFFFFFFFFu;
+constexpr uint32_t kEvMany = 0xFFFFFFFEu;
+constexpr uint32_t kEvMaxSet = (1u << 26) - 2;
 constexpr uint32_t kMaxChunk = 2048;      // 32 segments: one bit each in a chunk mask
 constexpr uint32_t kDenseMatches = AC_DENSE_SEGMENT_MATCHES;  // listed last, one wave each
 constexpr uint32_t kLdsPad = 1024;        // zero bytes after an LDS table (u8 codes >= sigma)
@@ -153,9 +161,14 @@ __device__ __forceinline__ void walk_count(const UTable<PLACE> &tab, const UText
         for (uint32_t p = 0; p < PD; ++p)
             nx[c][p] = 4 * p < wpc ? txt.vec_once(w0[c] + 4 * p) : u32x4{0, 0, 0, 0};
     for (uint32_t g = 0; g < spc; ++g) {
-        uint32_t qs[CH][4], sm[CH];
+        uint32_t qs[CH][4], sm[CH], ev[CH][kEvSlots], ne[CH];
 #pragma unroll
-        for (int c = 0; c < CH; ++c) sm[c] = 0;
+        for (int c = 0; c < CH; ++c) {
+            sm[c] = 0;
+            ne[c] = 0;
+#pragma unroll
+            for (uint32_t e = 0; e < kEvSlots; ++e) ev[c][e] = kEvNone;
+        }
 #pragma unroll
         for (uint32_t v = 0; v < WPS; v += 4) {
             u32x4 x4[CH];
@@ -197,6 +210,12 @@ __device__ __forceinline__ void walk_count(const UTable<PLACE> &tab, const UText
                             if (st[c][k] >= fo && p0 + k < in[c].lim) {
                                 const uint32_t o = row_state(st[c][k], tz, inv) - fo_state;
                                 sm[c] += out_off[o + 1] - out_off[o];
+                                const uint32_t e = o <= kEvMaxSet ? o << 6 | ((v + q) * SPW + k)
+                                                                  : kEvMany;
+#pragma unroll
+                                for (uint32_t u = 0; u < kEvSlots; ++u)
+                                    ev[c][u] = ne[c] == u ? e : ev[c][u];
+                                ne[c] = e == kEvMany ? kEvSlots + 1 : ne[c] + 1;
                             }
                         }
                     }
@@ -207,7 +226,10 @@ __device__ __forceinline__ void walk_count(const UTable<PLACE> &tab, const UText
         for (int c = 0; c < CH; ++c) {
             if (sm[c]) {
                 r[c].mask |= 1u << g;
-                seg_state[in[c].seg0 + g] = u32x4{qs[c][0], qs[c][1], qs[c][2], qs[c][3]};
+                u32x4 *rec = seg_state + 2 * (in[c].seg0 + g);
+                rec[0] = u32x4{qs[c][0], qs[c][1], qs[c][2], qs[c][3]};
+                rec[1] = ne[c] <= kEvSlots ? u32x4{ev[c][0], ev[c][1], ev[c][2], ev[c][3]}
+                                           : u32x4{kEvMany, kEvNone, kEvNone, kEvNone};
                 seg_m[in[c].seg0 + g] = sm[c];
                 r[c].dense += sm[c] >= kDenseMatches;
             }
@@ -269,12 +291,15 @@ __device__ __forceinline__ void walk_count2(rsrc_t g1, const UText &txt,
         for (uint32_t p = 0; p < PD; ++p)
             nx[c][p] = 4 * p < wpc ? txt.vec_once(w0[c] + 4 * p) : u32x4{0, 0, 0, 0};
     for (uint32_t g = 0; g < spc; ++g) {
-        uint32_t qs[CH][4], sm[CH];
+        uint32_t qs[CH][4], sm[CH], ev[CH][kEvSlots], ne[CH];
         u32x4 x4[CH];
         const uint32_t wn = g * WPS + 4 * PD;
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
             sm[c] = 0;
+            ne[c] = 0;
+#pragma unroll
+            for (uint32_t e = 0; e < kEvSlots; ++e) ev[c][e] = kEvNone;
             x4[c] = nx[c][0];
 #pragma unroll
             for (uint32_t p = 0; p + 1 < PD; ++p) nx[c][p] = nx[c][p + 1];
@@ -308,6 +333,11 @@ __device__ __forceinline__ void walk_count2(rsrc_t g1, const UText &txt,
                         if (t >= fo1 && p0 + k < in[c].lim) {
                             const uint32_t o = row_state(t, tz, inv) - fo_state;
                             sm[c] += out_off[o + 1] - out_off[o];
+                            const uint32_t e = o <= kEvMaxSet ? o << 6 | (q * SPW + k) : kEvMany;
+#pragma unroll
+                            for (uint32_t u = 0; u < kEvSlots; ++u)
+                                ev[c][u] = ne[c] == u ? e : ev[c][u];
+                            ne[c] = e == kEvMany ? kEvSlots + 1 : ne[c] + 1;
                         }
                     }
                 }
@@ -317,7 +347,10 @@ __device__ __forceinline__ void walk_count2(rsrc_t g1, const UText &txt,
         for (int c = 0; c < CH; ++c) {
             if (sm[c]) {
                 r[c].mask |= 1u << g;
-                seg_state[in[c].seg0 + g] = u32x4{qs[c][0], qs[c][1], qs[c][2], qs[c][3]};
+                u32x4 *rec = seg_state + 2 * (in[c].seg0 + g);
+                rec[0] = u32x4{qs[c][0], qs[c][1], qs[c][2], qs[c][3]};
+                rec[1] = ne[c] <= kEvSlots ? u32x4{ev[c][0], ev[c][1], ev[c][2], ev[c][3]}
+                                           : u32x4{kEvMany, kEvNone, kEvNone, kEvNone};
                 seg_m[in[c].seg0 + g] = sm[c];
                 r[c].dense += sm[c] >= kDenseMatches;
             }
@@ -568,7 +601,7 @@ __global__ __launch_bounds__(kMaxCountThreads) void k_scatter(
             const uint32_t sm = seg_m[gs];
             const uint32_t kk = sm >= kDenseMatches ? kd++ : ks++;
             list_seg[kk] = j * spc + i;
-            list_state[kk] = seg_state[gs];
+            list_state[kk] = seg_state[2 * gs];
             list_moff[kk] = off;
             if constexpr (BATCH) list_inst[kk] = inst;
             off += sm;
@@ -616,9 +649,11 @@ __device__ __forceinline__ void write_set(ac_match *__restrict__ out, unsigned l
     }
 }
 
-// Sparse part of the work list: four lanes per listed segment, lane q
-// walking quarter q (16 symbols) from the state the count pass stored for
-// it, so a segment costs 16 dependent lookups instead of 64.  A lane records
+// Sparse part of the work list: four lanes per listed segment.  When the
+// count pass kept the segment's output events (at most four), lane q takes
+// event q and no text is read.  Otherwise lane q walks quarter q (16
+// symbols) from the state the count pass stored for it, so a segment costs
+// 16 dependent lookups instead of 64.  A lane records
 // its output events (state, position) in LDS during the walk -- at most one
 // per position, so 16 slots always suffice -- and writes after the walk:
 // on gfx9 a wave's wait for a load also waits for its earlier stores, so a
@@ -631,11 +666,12 @@ template <int FMT, bool BATCH>
 __global__ __launch_bounds__(kEmitThreads) void k_emit(
     Inst single, const Inst *__restrict__ insts, const uint32_t *__restrict__ list_seg,
     const u32x4 *__restrict__ list_state, const unsigned long long *__restrict__ list_moff,
-    const uint32_t *__restrict__ list_inst, const unsigned long long *__restrict__ totals) {
+    const uint32_t *__restrict__ list_inst, const unsigned long long *__restrict__ totals,
+    const u32x4 *__restrict__ seg_rec, uint32_t spc) {
     constexpr uint32_t SPW = Fmt<FMT>::SPW;
     constexpr uint32_t WPS = kSeg / SPW;
     constexpr uint32_t WPQ = kQuarter / SPW;  // text words per quarter
-    __shared__ uint32_t ev_state[kQuarter][kEmitThreads];
+    __shared__ uint32_t ev_set[kQuarter][kEmitThreads];
     __shared__ uint8_t ev_pos[kQuarter][kEmitThreads];
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63;
@@ -661,6 +697,8 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
             const uint32_t lim = min(kSeg, I.n - e0);
             const uint32_t fo = I.fo_bytes, fos = I.fo_state, tz = I.div_tz, inv = I.div_inv;
             const uint32_t *out_off = I.out_off;
+            const uint32_t cb = BATCH ? I.chunk_base : 0u;
+            const u32x4 evs = seg_rec[2 * (cb * spc + seg) + 1];
             auto walk = [&](const auto &tab, const auto &txt) {
                 uint32_t st = q == 0 ? qs.x : q == 1 ? qs.y : q == 2 ? qs.z : qs.w;
 #pragma unroll
@@ -671,21 +709,29 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
                         st = tab(st + sym_bytes<FMT>(x, k));
                         const uint32_t p = q * kQuarter + w * SPW + k;
                         if (st >= fo && p < lim) {
-                            ev_state[ne][tid] = st;
+                            ev_set[ne][tid] = row_state(st, tz, inv) - fos;
                             ev_pos[ne][tid] = (uint8_t)p;
                             ++ne;
                         }
                     }
                 }
             };
-            if constexpr (BATCH) {
+            if (evs.x != kEvMany) {
+                // the count pass's events: event q for lane q
+                const uint32_t e = q == 0 ? evs.x : q == 1 ? evs.y : q == 2 ? evs.z : evs.w;
+                if (e != kEvNone) {
+                    ev_set[0][tid] = e >> 6;
+                    ev_pos[0][tid] = (uint8_t)(e & 63u);
+                    ne = 1;
+                }
+            } else if constexpr (BATCH) {
                 walk(LTable{I.delta, I.table_bytes}, LText{(const uint32_t *)I.text, I.text_bytes4});
             } else {
                 walk(UTable<PL_GLOBAL>{make_rsrc(single.delta, single.table_bytes), 0, 0},
                      UText{make_rsrc(single.text, single.text_bytes4), single.text_bytes4});
             }
             for (uint32_t j = 0; j < ne; ++j) {
-                const uint32_t o = row_state(ev_state[j][tid], tz, inv) - fos;
+                const uint32_t o = ev_set[j][tid];
                 matches += out_off[o + 1] - out_off[o];
             }
         }
@@ -696,11 +742,10 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
         const uint32_t before = (q >= 1 ? m1 : 0u) + (q >= 2 ? m2 : 0u) + (q >= 3 ? m3 : 0u);
         if (act && ne) {
             const Inst &I = BATCH ? insts[list_inst[idx]] : single;
-            const uint32_t fos = I.fo_state, tz = I.div_tz, inv = I.div_inv;
             const uint32_t *out_off = I.out_off;
             unsigned long long off = off0 + before;
             for (uint32_t j = 0; j < ne; ++j) {
-                const uint32_t o = row_state(ev_state[j][tid], tz, inv) - fos;
+                const uint32_t o = ev_set[j][tid];
                 const uint32_t a = out_off[o], len = out_off[o + 1] - a;
                 write_set(I.out, off, I.capacity, I.out_ids, a, len, e0 + ev_pos[j][tid]);
                 off += len;
@@ -1208,7 +1253,7 @@ struct Geom {
 
 struct Workspace {
     uint32_t *cnt, *mask;                 // per chunk
-    u32x4 *seg_state;                     // per segment: states entering its quarters
+    u32x4 *seg_state;                     // per segment: quarter states, then events
     uint32_t *seg_m;                      // per segment: matches (written where > 0)
     unsigned long long *tile_m;           // per tile
     uint32_t *tile_zs, *tile_zd;
@@ -1231,7 +1276,7 @@ static uint64_t ws_layout(const Geom &g, bool batch, char *base, Workspace *w) {
     Workspace t;
     t.cnt = (uint32_t *)take(4 * C);
     t.mask = (uint32_t *)take(4 * C);
-    t.seg_state = (u32x4 *)take(16 * S);
+    t.seg_state = (u32x4 *)take(32 * S);
     t.seg_m = (uint32_t *)take(4 * S);
     t.tile_m = (unsigned long long *)take(8 * T);
     t.tile_zs = (uint32_t *)take(4 * T);
@@ -1314,10 +1359,9 @@ static int resolve_geom(const ac_dict *const *dicts, const uint64_t *ns, uint32_
     g->warm = (max_len - 1 + spw - 1) / spw;
     g->threads = (tune && tune->block_threads) ? tune->block_threads : 1024u;
     if (g->threads < 64 || g->threads > kMaxCountThreads || g->threads % 64) return AC_E_INVALID;
-    // two chains per lane for 2-bit text; one for byte text, whose
-    // dictionaries are wider rows (sigma 20) and whose lanes already walk
-    // short chunks
-    g->chains = (tune && tune->chains) ? tune->chains : (fmt == AC_TEXT_2BIT ? 2u : 1u);
+    // one chain per lane by default: with the output events the count walk
+    // keeps per segment, two chains need about 120 VGPRs and gain nothing
+    g->chains = (tune && tune->chains) ? tune->chains : 1u;
     if (g->chains != 1 && g->chains != 2 && g->chains != 4) return AC_E_INVALID;
     const uint32_t per_tile = g->threads * g->chains;  // chunks per tile
     uint32_t chunk = tune ? tune->chunk : 0;
@@ -1452,7 +1496,8 @@ static int launch_single(const Geom &g, const Inst &I, const Workspace &w, hipSt
     {
         KTimer tm(AC_K_EMIT, st);
         hipLaunchKernelGGL((k_emit<FMT, false>), dim3(g.grid_emit), dim3(kEmitThreads), 0, st, I,
-                           nullptr, w.list_seg, w.list_state, w.list_moff, nullptr, w.totals);
+                           nullptr, w.list_seg, w.list_state, w.list_moff, nullptr, w.totals,
+                           w.seg_state, g.chunk / kSeg);
     }
     {
         KTimer tm(AC_K_EMIT_DENSE, st);
