@@ -192,12 +192,22 @@ def main():
     }
     rooflines = {k: v for k, v in rooflines.items() if v}
     rooflines["count"]["lookups_per_s"] = n / (avg["count"] * 1e-3)
+    # nominal LDS lookup peak: 32 banks x 4 B per clock per CU, conflict-free
+    lds_lookup_peak = 32 * CUS * CLOCK_GHZ * 1e9
+    rooflines["count"]["lds_lookup_peak_per_s"] = lds_lookup_peak
+    rooflines["count"]["lookup_frac"] = rooflines["count"]["lookups_per_s"] / lds_lookup_peak
     dom = max(rooflines, key=lambda k: rooflines[k]["avg_us"])
     r = rooflines[dom]
     roofline = {"bound": r["bound"], "achieved": round(r["achieved"], 1), "peak": r["peak"],
                 "unit": r["unit"], "frac": round(r["achieved"] / r["peak"], 4),
                 "traffic": measured_traffic(dom, "dna_dense"), "kernel": dom,
                 "kernel_avg_us": round(r["avg_us"], 2)}
+    if dom == "count":
+        # the count pass moves little HBM data; what bounds it is one
+        # dependent table lookup per base (LDS, or L2 for rows not in LDS)
+        roofline["lookups"] = {"achieved_per_s": round(r["lookups_per_s"], 1),
+                               "lds_peak_per_s": lds_lookup_peak,
+                               "frac": round(r["lookup_frac"], 4)}
 
     cus, lds = ac.ac_device_info()
     lds_limit = lds - 512
