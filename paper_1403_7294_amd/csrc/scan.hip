@@ -117,7 +117,8 @@ struct ChainIn {
 // segment with matches the entry state and the count are stored.
 template <int FMT, int PLACE, int CH>
 __device__ __forceinline__ void walk_count(const UTable<PLACE> &tab, const UText &txt,
-                                           const uint32_t *__restrict__ out_off, uint32_t fo,
+                                           const uint32_t *__restrict__ out_off,
+                                           uint32_t out_off_bytes, uint32_t fo,
                                            uint32_t fo_state, uint32_t tz, uint32_t inv,
                                            uint32_t chunk, uint32_t warm, const ChainIn (&in)[CH],
                                            u32x4 *__restrict__ seg_state,
@@ -125,6 +126,7 @@ __device__ __forceinline__ void walk_count(const UTable<PLACE> &tab, const UText
     constexpr uint32_t SPW = Fmt<FMT>::SPW;
     constexpr uint32_t WPS = kSeg / SPW;  // text words per segment
     const uint32_t wpc = chunk / SPW, spc = chunk / kSeg;
+    const rsrc_t offs = make_rsrc(out_off, out_off_bytes);
     uint32_t s[CH], w0[CH];
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
@@ -203,15 +205,29 @@ __device__ __forceinline__ void walk_count(const UTable<PLACE> &tab, const UText
 #pragma unroll
                 for (int c = 0; c < CH; ++c) {
                     if (acc[c] >= fo) {
-                        // some state of this word has an output set: add sizes
+                        // some state of this word has an output set: add the
+                        // set sizes.  The offset loads of all positions are
+                        // issued before the first is used, so the word costs
+                        // one memory latency, not one per output state.
                         const uint32_t p0 = (g * WPS + v + q) * SPW;
+                        uint32_t o[SPW], lo[SPW], hi[SPW];
 #pragma unroll
                         for (uint32_t k = 0; k < SPW; ++k) {
-                            if (st[c][k] >= fo && p0 + k < in[c].lim) {
-                                const uint32_t o = row_state(st[c][k], tz, inv) - fo_state;
-                                sm[c] += out_off[o + 1] - out_off[o];
-                                const uint32_t e = o <= kEvMaxSet ? o << 6 | ((v + q) * SPW + k)
-                                                                  : kEvMany;
+                            const bool hit = st[c][k] >= fo && p0 + k < in[c].lim;
+                            o[k] = hit ? row_state(st[c][k], tz, inv) - fo_state : kEvNone;
+                            // out of range for positions without output: no
+                            // memory access, value 0
+                            const uint32_t a = hit ? o[k] * 4u : 0xFFFFFFF0u;
+                            lo[k] = buf_load(offs, a);
+                            hi[k] = buf_load(offs, a + 4u);
+                        }
+#pragma unroll
+                        for (uint32_t k = 0; k < SPW; ++k) {
+                            sm[c] += hi[k] - lo[k];
+                            if (o[k] != kEvNone) {
+                                const uint32_t e = o[k] <= kEvMaxSet
+                                                       ? o[k] << 6 | ((v + q) * SPW + k)
+                                                       : kEvMany;
 #pragma unroll
                                 for (uint32_t u = 0; u < kEvSlots; ++u)
                                     ev[c][u] = ne[c] == u ? e : ev[c][u];
@@ -243,13 +259,15 @@ __device__ __forceinline__ void walk_count(const UTable<PLACE> &tab, const UText
 // symbols (state * 64) with bit 31 set when the state after the first symbol
 // has an output set, so a running max over the entries of a word exceeds the
 // first output row offset exactly when some state entered in the word has
-// an output set.  Such a word (rare) is walked again one symbol at a time
-// through the single-symbol table to add the output-set sizes.  Quarter
+// an output set.  For such a word the states after the first symbol of the
+// flagged pairs are read from the single-symbol table (all at once), then
+// the output-set sizes of every state entered.  Quarter
 // states are stored as single-symbol row offsets, which the emit kernels
 // read.
 template <int CH>
 __device__ __forceinline__ void walk_count2(rsrc_t g1, const UText &txt,
-                                            const uint32_t *__restrict__ out_off, uint32_t fo1,
+                                            const uint32_t *__restrict__ out_off,
+                                            uint32_t out_off_bytes, uint32_t fo1,
                                             uint32_t fo2, uint32_t fo_state, uint32_t tz,
                                             uint32_t inv, uint32_t chunk, uint32_t warm,
                                             const ChainIn (&in)[CH], u32x4 *__restrict__ seg_state,
@@ -258,6 +276,7 @@ __device__ __forceinline__ void walk_count2(rsrc_t g1, const UText &txt,
     constexpr uint32_t WPS = kSeg / SPW;  // words per segment (4)
     constexpr uint32_t kMask = 0x7FFFFFFFu;
     const uint32_t wpc = chunk / SPW, spc = chunk / kSeg;
+    const rsrc_t offs = make_rsrc(out_off, out_off_bytes);
     uint32_t s[CH], w0[CH];
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
@@ -307,7 +326,7 @@ __device__ __forceinline__ void walk_count2(rsrc_t g1, const UText &txt,
         }
 #pragma unroll
         for (uint32_t q = 0; q < WPS; ++q) {
-            uint32_t acc[CH], s_in[CH];
+            uint32_t acc[CH], s_in[CH], pe[CH][SPW / 2];
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
                 s_in[c] = s[c];
@@ -319,6 +338,7 @@ __device__ __forceinline__ void walk_count2(rsrc_t g1, const UText &txt,
 #pragma unroll
                 for (int c = 0; c < CH; ++c) {
                     const uint32_t e = lds_load(s[c] + ((x4[c][q] >> (4 * k)) & 15u) * 4u);
+                    pe[c][k] = e;
                     acc[c] = acc[c] > e ? acc[c] : e;
                     s[c] = e & kMask;
                 }
@@ -326,14 +346,34 @@ __device__ __forceinline__ void walk_count2(rsrc_t g1, const UText &txt,
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
                 if (acc[c] >= fo2) {
+                    // single-symbol states of the word: the state after each
+                    // pair is known; the one after the first symbol of a
+                    // flagged pair is read from the single-symbol table, all
+                    // such reads issued together
                     const uint32_t p0 = (g * WPS + q) * SPW;
-                    uint32_t t = s_in[c] >> 2;
+                    uint32_t t1[SPW];
+#pragma unroll
+                    for (uint32_t k = 0; k < SPW / 2; ++k) {
+                        const uint32_t prev = (k ? pe[c][k - 1] & kMask : s_in[c]) >> 2;
+                        const uint32_t a1 = (x4[c][q] >> (4 * k)) & 3u;
+                        t1[2 * k] = (pe[c][k] & ~kMask) ? buf_load(g1, prev + a1 * 4u) : 0u;
+                        t1[2 * k + 1] = (pe[c][k] & kMask) >> 2;
+                    }
+                    uint32_t o[SPW], lo[SPW], hi[SPW];
+#pragma unroll
                     for (uint32_t k = 0; k < SPW; ++k) {
-                        t = buf_load(g1, t + ((x4[c][q] >> (2 * k)) & 3u) * 4u);
-                        if (t >= fo1 && p0 + k < in[c].lim) {
-                            const uint32_t o = row_state(t, tz, inv) - fo_state;
-                            sm[c] += out_off[o + 1] - out_off[o];
-                            const uint32_t e = o <= kEvMaxSet ? o << 6 | (q * SPW + k) : kEvMany;
+                        const bool hit = t1[k] >= fo1 && p0 + k < in[c].lim;
+                        o[k] = hit ? row_state(t1[k], tz, inv) - fo_state : kEvNone;
+                        const uint32_t a = hit ? o[k] * 4u : 0xFFFFFFF0u;
+                        lo[k] = buf_load(offs, a);
+                        hi[k] = buf_load(offs, a + 4u);
+                    }
+#pragma unroll
+                    for (uint32_t k = 0; k < SPW; ++k) {
+                        sm[c] += hi[k] - lo[k];
+                        if (o[k] != kEvNone) {
+                            const uint32_t e = o[k] <= kEvMaxSet ? o[k] << 6 | (q * SPW + k)
+                                                                 : kEvMany;
 #pragma unroll
                             for (uint32_t u = 0; u < kEvSlots; ++u)
                                 ev[c][u] = ne[c] == u ? e : ev[c][u];
@@ -434,6 +474,8 @@ __global__ __launch_bounds__(kMaxCountThreads) void k_count(
         const UText txt{make_rsrc(uniform(I.text), tb4), tb4};
         const uint32_t *out_off = uniform(I.out_off);
         const uint32_t fo = uniform(I.fo_bytes), fos = uniform(I.fo_state);
+        // bytes of the output-set offsets (one entry per output state, + 1)
+        const uint32_t oob = (uniform(I.table_bytes) / row - fos + 1) * 4u;
         const uint32_t tz = uniform(I.div_tz), inv = uniform(I.div_inv);
         const uint32_t cbase = uniform(I.chunk_base);
         ChainIn in[CH];
@@ -450,20 +492,23 @@ __global__ __launch_bounds__(kMaxCountThreads) void k_count(
         bool done = false;
         if constexpr (FMT == AC_TEXT_2BIT) {
             if (uniform(I.stride2)) {
-                walk_count2<CH>(gtab, txt, out_off, fo, uniform(I.fo2_bytes), fos, tz, inv, chunk,
-                                warm, in, seg_state, seg_m, co);
+                walk_count2<CH>(gtab, txt, out_off, oob, fo, uniform(I.fo2_bytes), fos, tz, inv,
+                                chunk, warm, in, seg_state, seg_m, co);
                 done = true;
             }
         }
         if (done) {
         } else if (lds_all) {
-            walk_count<FMT, PL_LDS, CH>(UTable<PL_LDS>{gtab, hot, row}, txt, out_off, fo, fos, tz, inv,
+            walk_count<FMT, PL_LDS, CH>(UTable<PL_LDS>{gtab, hot, row}, txt, out_off, oob, fo, fos,
+                                        tz, inv,
                                         chunk, warm, in, seg_state, seg_m, co);
         } else if (hot == 0) {
-            walk_count<FMT, PL_GLOBAL, CH>(UTable<PL_GLOBAL>{gtab, 0, row}, txt, out_off, fo, fos, tz,
+            walk_count<FMT, PL_GLOBAL, CH>(UTable<PL_GLOBAL>{gtab, 0, row}, txt, out_off, oob, fo,
+                                           fos, tz,
                                            inv, chunk, warm, in, seg_state, seg_m, co);
         } else {
-            walk_count<FMT, PL_HYBRID, CH>(UTable<PL_HYBRID>{gtab, hot, row}, txt, out_off, fo, fos,
+            walk_count<FMT, PL_HYBRID, CH>(UTable<PL_HYBRID>{gtab, hot, row}, txt, out_off, oob, fo,
+                                           fos,
                                            tz, inv, chunk, warm, in, seg_state, seg_m, co);
         }
         unsigned long long m = 0;
