@@ -67,6 +67,7 @@ struct ac_dict {
     uint32_t *d_delta = nullptr;    // states*sigma row byte offsets
     uint32_t *d_out_off = nullptr;
     uint32_t *d_out_ids = nullptr;
+    uint32_t *d_out_size = nullptr;  // |out(s)| per output state
     uint16_t *d_hot16 = nullptr;  // first hot16_rows rows as 16-bit ids (0xFFFF: see table)
     uint32_t hot16_rows = 0;
     // sigma 4 only, when it fits LDS: transitions over two symbols,

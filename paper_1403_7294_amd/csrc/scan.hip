@@ -64,6 +64,7 @@ struct Inst {
     const uint32_t *delta;  // row byte offsets: delta[s*sigma+a] = next*sigma*4
     const uint32_t *out_off;
     const uint32_t *out_ids;
+    const uint32_t *out_size;  // |out(s)| per output state (count pass)
     const uint16_t *hot16;   // 16-bit rows for the hybrid placement
     const uint8_t *text;
     ac_match *out;
@@ -117,8 +118,8 @@ struct ChainIn {
 // segment with matches the entry state and the count are stored.
 template <int FMT, int PLACE, int CH>
 __device__ __forceinline__ void walk_count(const UTable<PLACE> &tab, const UText &txt,
-                                           const uint32_t *__restrict__ out_off,
-                                           uint32_t out_off_bytes, uint32_t fo,
+                                           const uint32_t *__restrict__ out_size,
+                                           uint32_t out_size_bytes, uint32_t fo,
                                            uint32_t fo_state, uint32_t tz, uint32_t inv,
                                            uint32_t chunk, uint32_t warm, const ChainIn (&in)[CH],
                                            u32x4 *__restrict__ seg_state,
@@ -126,7 +127,7 @@ __device__ __forceinline__ void walk_count(const UTable<PLACE> &tab, const UText
     constexpr uint32_t SPW = Fmt<FMT>::SPW;
     constexpr uint32_t WPS = kSeg / SPW;  // text words per segment
     const uint32_t wpc = chunk / SPW, spc = chunk / kSeg;
-    const rsrc_t offs = make_rsrc(out_off, out_off_bytes);
+    const rsrc_t sizes = make_rsrc(out_size, out_size_bytes);
     uint32_t s[CH], w0[CH];
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
@@ -210,20 +211,18 @@ __device__ __forceinline__ void walk_count(const UTable<PLACE> &tab, const UText
                         // issued before the first is used, so the word costs
                         // one memory latency, not one per output state.
                         const uint32_t p0 = (g * WPS + v + q) * SPW;
-                        uint32_t o[SPW], lo[SPW], hi[SPW];
+                        uint32_t o[SPW], sz[SPW];
 #pragma unroll
                         for (uint32_t k = 0; k < SPW; ++k) {
                             const bool hit = st[c][k] >= fo && p0 + k < in[c].lim;
                             o[k] = hit ? row_state(st[c][k], tz, inv) - fo_state : kEvNone;
                             // out of range for positions without output: no
                             // memory access, value 0
-                            const uint32_t a = hit ? o[k] * 4u : 0xFFFFFFF0u;
-                            lo[k] = buf_load(offs, a);
-                            hi[k] = buf_load(offs, a + 4u);
+                            sz[k] = buf_load(sizes, hit ? o[k] * 4u : 0xFFFFFFF0u);
                         }
 #pragma unroll
                         for (uint32_t k = 0; k < SPW; ++k) {
-                            sm[c] += hi[k] - lo[k];
+                            sm[c] += sz[k];
                             if (o[k] != kEvNone) {
                                 const uint32_t e = o[k] <= kEvMaxSet
                                                        ? o[k] << 6 | ((v + q) * SPW + k)
@@ -266,8 +265,8 @@ __device__ __forceinline__ void walk_count(const UTable<PLACE> &tab, const UText
 // read.
 template <int CH>
 __device__ __forceinline__ void walk_count2(rsrc_t g1, const UText &txt,
-                                            const uint32_t *__restrict__ out_off,
-                                            uint32_t out_off_bytes, uint32_t fo1,
+                                            const uint32_t *__restrict__ out_size,
+                                            uint32_t out_size_bytes, uint32_t fo1,
                                             uint32_t fo2, uint32_t fo_state, uint32_t tz,
                                             uint32_t inv, uint32_t chunk, uint32_t warm,
                                             const ChainIn (&in)[CH], u32x4 *__restrict__ seg_state,
@@ -276,7 +275,7 @@ __device__ __forceinline__ void walk_count2(rsrc_t g1, const UText &txt,
     constexpr uint32_t WPS = kSeg / SPW;  // words per segment (4)
     constexpr uint32_t kMask = 0x7FFFFFFFu;
     const uint32_t wpc = chunk / SPW, spc = chunk / kSeg;
-    const rsrc_t offs = make_rsrc(out_off, out_off_bytes);
+    const rsrc_t sizes = make_rsrc(out_size, out_size_bytes);
     uint32_t s[CH], w0[CH];
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
@@ -359,18 +358,16 @@ __device__ __forceinline__ void walk_count2(rsrc_t g1, const UText &txt,
                         t1[2 * k] = (pe[c][k] & ~kMask) ? buf_load(g1, prev + a1 * 4u) : 0u;
                         t1[2 * k + 1] = (pe[c][k] & kMask) >> 2;
                     }
-                    uint32_t o[SPW], lo[SPW], hi[SPW];
+                    uint32_t o[SPW], sz[SPW];
 #pragma unroll
                     for (uint32_t k = 0; k < SPW; ++k) {
                         const bool hit = t1[k] >= fo1 && p0 + k < in[c].lim;
                         o[k] = hit ? row_state(t1[k], tz, inv) - fo_state : kEvNone;
-                        const uint32_t a = hit ? o[k] * 4u : 0xFFFFFFF0u;
-                        lo[k] = buf_load(offs, a);
-                        hi[k] = buf_load(offs, a + 4u);
+                        sz[k] = buf_load(sizes, hit ? o[k] * 4u : 0xFFFFFFF0u);
                     }
 #pragma unroll
                     for (uint32_t k = 0; k < SPW; ++k) {
-                        sm[c] += hi[k] - lo[k];
+                        sm[c] += sz[k];
                         if (o[k] != kEvNone) {
                             const uint32_t e = o[k] <= kEvMaxSet ? o[k] << 6 | (q * SPW + k)
                                                                  : kEvMany;
@@ -472,10 +469,10 @@ __global__ __launch_bounds__(kMaxCountThreads) void k_count(
         const uint32_t n = uniform(I.n);
         const uint32_t tb4 = uniform(I.text_bytes4);
         const UText txt{make_rsrc(uniform(I.text), tb4), tb4};
-        const uint32_t *out_off = uniform(I.out_off);
+        const uint32_t *out_size = uniform(I.out_size);
         const uint32_t fo = uniform(I.fo_bytes), fos = uniform(I.fo_state);
-        // bytes of the output-set offsets (one entry per output state, + 1)
-        const uint32_t oob = (uniform(I.table_bytes) / row - fos + 1) * 4u;
+        // bytes of the output-set sizes (one entry per output state)
+        const uint32_t size_bytes = (uniform(I.table_bytes) / row - fos) * 4u;
         const uint32_t tz = uniform(I.div_tz), inv = uniform(I.div_inv);
         const uint32_t cbase = uniform(I.chunk_base);
         ChainIn in[CH];
@@ -492,24 +489,23 @@ __global__ __launch_bounds__(kMaxCountThreads) void k_count(
         bool done = false;
         if constexpr (FMT == AC_TEXT_2BIT) {
             if (uniform(I.stride2)) {
-                walk_count2<CH>(gtab, txt, out_off, oob, fo, uniform(I.fo2_bytes), fos, tz, inv,
-                                chunk, warm, in, seg_state, seg_m, co);
+                walk_count2<CH>(gtab, txt, out_size, size_bytes, fo, uniform(I.fo2_bytes), fos, tz,
+                                inv, chunk, warm, in, seg_state, seg_m, co);
                 done = true;
             }
         }
         if (done) {
         } else if (lds_all) {
-            walk_count<FMT, PL_LDS, CH>(UTable<PL_LDS>{gtab, hot, row}, txt, out_off, oob, fo, fos,
-                                        tz, inv,
-                                        chunk, warm, in, seg_state, seg_m, co);
+            walk_count<FMT, PL_LDS, CH>(UTable<PL_LDS>{gtab, hot, row}, txt, out_size, size_bytes,
+                                        fo, fos, tz, inv, chunk, warm, in, seg_state, seg_m, co);
         } else if (hot == 0) {
-            walk_count<FMT, PL_GLOBAL, CH>(UTable<PL_GLOBAL>{gtab, 0, row}, txt, out_off, oob, fo,
-                                           fos, tz,
-                                           inv, chunk, warm, in, seg_state, seg_m, co);
+            walk_count<FMT, PL_GLOBAL, CH>(UTable<PL_GLOBAL>{gtab, 0, row}, txt, out_size,
+                                           size_bytes, fo, fos, tz, inv, chunk, warm, in,
+                                           seg_state, seg_m, co);
         } else {
-            walk_count<FMT, PL_HYBRID, CH>(UTable<PL_HYBRID>{gtab, hot, row}, txt, out_off, oob, fo,
-                                           fos,
-                                           tz, inv, chunk, warm, in, seg_state, seg_m, co);
+            walk_count<FMT, PL_HYBRID, CH>(UTable<PL_HYBRID>{gtab, hot, row}, txt, out_size,
+                                           size_bytes, fo, fos, tz, inv, chunk, warm, in,
+                                           seg_state, seg_m, co);
         }
         unsigned long long m = 0;
         uint32_t zs = 0, zd = 0;
@@ -1181,10 +1177,13 @@ int upload_dict(ac_dict *d) {
         }
     }
     const size_t off_bytes = T.out_off.size() * 4;
+    std::vector<uint32_t> sizes(std::max<size_t>(1, T.out_off.size() - 1), 0);
+    for (size_t i = 0; i + 1 < T.out_off.size(); ++i) sizes[i] = T.out_off[i + 1] - T.out_off[i];
     const size_t ids_bytes = std::max<size_t>(4, T.out_ids.size() * 4);
     if (hipMalloc((void **)&d->d_delta, rows.size() * 4) != hipSuccess ||
         hipMalloc((void **)&d->d_out_off, off_bytes) != hipSuccess ||
         hipMalloc((void **)&d->d_out_ids, ids_bytes) != hipSuccess ||
+        hipMalloc((void **)&d->d_out_size, sizes.size() * 4) != hipSuccess ||
         hipMalloc((void **)&d->d_hot16, hot16.size() * 2) != hipSuccess ||
         (!d2.empty() && hipMalloc((void **)&d->d_delta2, d2.size() * 4) != hipSuccess) ||
         (!go.empty() && (hipMalloc((void **)&d->d_go, go.size() * 4) != hipSuccess ||
@@ -1196,6 +1195,8 @@ int upload_dict(ac_dict *d) {
     }
     if (hipMemcpy(d->d_delta, rows.data(), rows.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(d->d_out_off, T.out_off.data(), off_bytes, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d->d_out_size, sizes.data(), sizes.size() * 4, hipMemcpyHostToDevice) !=
+            hipSuccess ||
         (!T.out_ids.empty() &&
          hipMemcpy(d->d_out_ids, T.out_ids.data(), T.out_ids.size() * 4, hipMemcpyHostToDevice) !=
              hipSuccess) ||
@@ -1222,6 +1223,8 @@ void release_dict(ac_dict *d) {
     if (d->d_delta) (void)hipFree(d->d_delta);
     if (d->d_out_off) (void)hipFree(d->d_out_off);
     if (d->d_out_ids) (void)hipFree(d->d_out_ids);
+    if (d->d_out_size) (void)hipFree(d->d_out_size);
+    d->d_out_size = nullptr;
     if (d->d_hot16) (void)hipFree(d->d_hot16);
     if (d->d_delta2) (void)hipFree(d->d_delta2);
     if (d->d_go) (void)hipFree(d->d_go);
@@ -1455,6 +1458,7 @@ static void fill_inst(const ac_dict *d, const void *text, uint64_t n, uint32_t f
     I->delta = d->d_delta;
     I->out_off = d->d_out_off;
     I->out_ids = d->d_out_ids;
+    I->out_size = d->d_out_size;
     I->text = (const uint8_t *)text;
     I->out = out;
     I->count = (unsigned long long *)count;
