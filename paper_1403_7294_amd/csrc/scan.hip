@@ -211,6 +211,17 @@ __device__ __forceinline__ void walk_count(const UTable<PLACE> &tab, const UText
                         // issued before the first is used, so the word costs
                         // one memory latency, not one per output state.
                         const uint32_t p0 = (g * WPS + v + q) * SPW;
+                        // one output state over the whole word (the inside
+                        // of a dense run): one size load, no events kept
+                        bool same = p0 + SPW <= in[c].lim;
+#pragma unroll
+                        for (uint32_t k = 1; k < SPW; ++k) same = same && st[c][k] == st[c][0];
+                        if (same) {
+                            const uint32_t o0 = row_state(st[c][0], tz, inv) - fo_state;
+                            sm[c] += SPW * buf_load(sizes, o0 * 4u);
+                            ne[c] = kEvSlots + 1;
+                            continue;
+                        }
                         uint32_t o[SPW], sz[SPW];
 #pragma unroll
                         for (uint32_t k = 0; k < SPW; ++k) {
