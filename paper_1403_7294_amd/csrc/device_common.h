@@ -115,6 +115,15 @@ __device__ __forceinline__ void block_excl_scan3(Scan3 v, Scan3 *excl, Scan3 *to
 __device__ __forceinline__ uint32_t row_state(uint32_t e, uint32_t tz, uint32_t inv) {
     return (e >> tz) * inv;
 }
+// The same where the text format fixes sigma: 2-bit text means sigma 4,
+// rows of 16 bytes, so the state is a shift (no multiply).
+template <int FMT>
+__device__ __forceinline__ uint32_t row_state_f(uint32_t e, uint32_t tz, uint32_t inv) {
+    if constexpr (FMT == AC_TEXT_2BIT)
+        return e >> 4;
+    else
+        return row_state(e, tz, inv);
+}
 
 template <int FMT>
 struct Fmt {

@@ -217,7 +217,7 @@ __device__ __forceinline__ void walk_count(const UTable<PLACE> &tab, const UText
 #pragma unroll
                         for (uint32_t k = 1; k < SPW; ++k) same = same && st[c][k] == st[c][0];
                         if (same) {
-                            const uint32_t o0 = row_state(st[c][0], tz, inv) - fo_state;
+                            const uint32_t o0 = row_state_f<FMT>(st[c][0], tz, inv) - fo_state;
                             sm[c] += SPW * buf_load(sizes, o0 * 4u);
                             ne[c] = kEvSlots + 1;
                             continue;
@@ -226,7 +226,7 @@ __device__ __forceinline__ void walk_count(const UTable<PLACE> &tab, const UText
 #pragma unroll
                         for (uint32_t k = 0; k < SPW; ++k) {
                             const bool hit = st[c][k] >= fo && p0 + k < in[c].lim;
-                            o[k] = hit ? row_state(st[c][k], tz, inv) - fo_state : kEvNone;
+                            o[k] = hit ? row_state_f<FMT>(st[c][k], tz, inv) - fo_state : kEvNone;
                             // out of range for positions without output: no
                             // memory access, value 0
                             sz[k] = buf_load(sizes, hit ? o[k] * 4u : 0xFFFFFFF0u);
@@ -373,7 +373,7 @@ __device__ __forceinline__ void walk_count2(rsrc_t g1, const UText &txt,
 #pragma unroll
                     for (uint32_t k = 0; k < SPW; ++k) {
                         const bool hit = t1[k] >= fo1 && p0 + k < in[c].lim;
-                        o[k] = hit ? row_state(t1[k], tz, inv) - fo_state : kEvNone;
+                        o[k] = hit ? (t1[k] >> 4) - fo_state : kEvNone;
                         sz[k] = buf_load(sizes, hit ? o[k] * 4u : 0xFFFFFFF0u);
                     }
 #pragma unroll
