@@ -1025,14 +1025,16 @@ __global__ __launch_bounds__(256) void k_encode(const uint8_t *__restrict__ in, 
     }
 }
 
-// DNA letters -> 2-bit codes, 64 letters per thread: four 16-byte
-// non-temporal loads, one 16-byte store.  Four letters are handled per 32-bit
+// DNA letters -> 2-bit codes, 64 letters per thread.  A wave covers 4096
+// letters: load q of lane i reads the 16 letters at wave base + 1024 q + 16 i
+// (four fully coalesced 1 KB loads per wave, non-temporal), and each 16
+// letters become one 32-bit store.  Four letters are handled per 32-bit
 // word at once: code = ((ch>>1) ^ (ch>>2)) & 3 in every byte, then the four
 // 2-bit fields are gathered into one byte.  A byte is valid when (ch | 0x20)
 // is one of a c g t; the exact per-byte zero test
 // z(v) = ~(((v & 0x7F..) + 0x7F..) | v) & 0x80.. has no carries between
-// bytes.  Letters past n read as 0 through the buffer resource and are
-// neither counted nor stored.
+// bytes.  The last partial wave (and unaligned buffers) take byte loads and
+// stores, with letters past n neither counted nor stored.
 __device__ __forceinline__ uint32_t zero_bytes(uint32_t v) {
     return ~(((v & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | v) & 0x80808080u;
 }
@@ -1041,18 +1043,36 @@ __global__ __launch_bounds__(256) void k_encode_dna2(const uint8_t *__restrict__
                                                      uint8_t *__restrict__ out,
                                                      unsigned long long *invalid) {
     constexpr int kNonTemporal = 2;
-    const uint64_t p = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 64u;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t wb = ((uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u)) * 64u;
     uint32_t bad = 0;
-    if (p < n) {
+    const bool wfull = wb + 4096 <= n && (((uintptr_t)in) & 15) == 0 && (((uintptr_t)out) & 3) == 0;
+    if (wfull) {
+        const rsrc_t r = make_rsrc(in, (uint32_t)n);
         u32x4 v[4];
-        if (p + 64 <= n && (((uintptr_t)in) & 15) == 0) {
-            const rsrc_t r = make_rsrc(in, (uint32_t)n);
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                v[q] = __builtin_amdgcn_raw_buffer_load_b128(r, (uint32_t)p + 16u * q, 0,
-                                                             kNonTemporal);
-        } else {
-            // the tail, or an input not 16-byte aligned: byte loads
+        for (int q = 0; q < 4; ++q)
+            v[q] = __builtin_amdgcn_raw_buffer_load_b128(
+                r, (uint32_t)(wb + 1024u * q + 16u * lane), 0, kNonTemporal);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            uint32_t packed = 0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const uint32_t x = v[q][w];
+                const uint32_t l = x | 0x20202020u;
+                const uint32_t ok = zero_bytes(l ^ 0x61616161u) | zero_bytes(l ^ 0x63636363u) |
+                                    zero_bytes(l ^ 0x67676767u) | zero_bytes(l ^ 0x74747474u);
+                bad += __builtin_popcount(~ok & 0x80808080u);
+                const uint32_t t = ((x >> 1) ^ (x >> 2)) & (ok >> 7) * 3u;
+                packed |= ((t | (t >> 6) | (t >> 12) | (t >> 18)) & 0xFFu) << (8 * w);
+            }
+            *(uint32_t *)(out + (wb + 1024u * q + 16u * lane) / 4) = packed;
+        }
+    } else {
+        const uint64_t p = wb + 64u * lane;
+        if (p < n) {
+            u32x4 v[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -1065,33 +1085,29 @@ __global__ __launch_bounds__(256) void k_encode_dna2(const uint8_t *__restrict__
                     }
                     v[q][w] = x;
                 }
-        }
-        u32x4 o;
+            u32x4 o;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            uint32_t packed = 0;
+            for (int q = 0; q < 4; ++q) {
+                uint32_t packed = 0;
 #pragma unroll
-            for (int w = 0; w < 4; ++w) {
-                const uint32_t x = v[q][w];
-                const uint32_t l = x | 0x20202020u;
-                const uint32_t ok = zero_bytes(l ^ 0x61616161u) | zero_bytes(l ^ 0x63636363u) |
-                                    zero_bytes(l ^ 0x67676767u) | zero_bytes(l ^ 0x74747474u);
-                const int64_t rem = (int64_t)n - (int64_t)(p + 16u * q + 4u * w);
-                const uint32_t live = rem >= 4 ? 0x80808080u
-                                      : rem <= 0 ? 0u
-                                                 : (uint32_t)((1ull << (8 * rem)) - 1u) & 0x80808080u;
-                bad += __builtin_popcount(~ok & live);
-                // invalid letters and letters past the end become code 0
-                const uint32_t t = ((x >> 1) ^ (x >> 2)) & ((ok & live) >> 7) * 3u;
-                packed |= ((t | (t >> 6) | (t >> 12) | (t >> 18)) & 0xFFu) << (8 * w);
+                for (int w = 0; w < 4; ++w) {
+                    const uint32_t x = v[q][w];
+                    const uint32_t l = x | 0x20202020u;
+                    const uint32_t ok = zero_bytes(l ^ 0x61616161u) | zero_bytes(l ^ 0x63636363u) |
+                                        zero_bytes(l ^ 0x67676767u) | zero_bytes(l ^ 0x74747474u);
+                    const int64_t rem = (int64_t)n - (int64_t)(p + 16u * q + 4u * w);
+                    const uint32_t live = rem >= 4 ? 0x80808080u
+                                          : rem <= 0 ? 0u
+                                                     : (uint32_t)((1ull << (8 * rem)) - 1u) &
+                                                           0x80808080u;
+                    bad += __builtin_popcount(~ok & live);
+                    const uint32_t t = ((x >> 1) ^ (x >> 2)) & ((ok & live) >> 7) * 3u;
+                    packed |= ((t | (t >> 6) | (t >> 12) | (t >> 18)) & 0xFFu) << (8 * w);
+                }
+                o[q] = packed;
             }
-            o[q] = packed;
-        }
-        const uint64_t ob = p / 4;            // 16 output bytes per thread
-        const uint64_t nb = (n + 3) / 4;
-        if (ob + 16 <= nb && (((uintptr_t)(out + ob)) & 15) == 0) {
-            *(u32x4 *)(out + ob) = o;
-        } else {
+            const uint64_t ob = p / 4;
+            const uint64_t nb = (n + 3) / 4;
 #pragma unroll
             for (int i = 0; i < 16; ++i)
                 if (ob + i < nb) out[ob + i] = (uint8_t)(o[i >> 2] >> (8 * (i & 3)));
