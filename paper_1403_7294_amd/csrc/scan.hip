@@ -222,6 +222,25 @@ __device__ __forceinline__ void walk_count(const UTable<PLACE> &tab, const UText
                             ne[c] = kEvSlots + 1;
                             continue;
                         }
+                        if constexpr (PLACE == PL_LDS) {
+                            // small tables: one position at a time (fewer
+                            // registers; the lookups are cheap)
+#pragma unroll
+                            for (uint32_t k = 0; k < SPW; ++k) {
+                                if (st[c][k] >= fo && p0 + k < in[c].lim) {
+                                    const uint32_t o =
+                                        row_state_f<FMT>(st[c][k], tz, inv) - fo_state;
+                                    sm[c] += buf_load(sizes, o * 4u);
+                                    const uint32_t e =
+                                        o <= kEvMaxSet ? o << 6 | ((v + q) * SPW + k) : kEvMany;
+#pragma unroll
+                                    for (uint32_t u = 0; u < kEvSlots; ++u)
+                                        ev[c][u] = ne[c] == u ? e : ev[c][u];
+                                    ne[c] = e == kEvMany ? kEvSlots + 1 : ne[c] + 1;
+                                }
+                            }
+                            continue;
+                        }
                         uint32_t o[SPW], sz[SPW];
 #pragma unroll
                         for (uint32_t k = 0; k < SPW; ++k) {
@@ -433,7 +452,10 @@ __device__ __forceinline__ void load_lds_table(rsrc_t g, uint32_t bytes) {
 // Persistent count kernel.  Block b takes a contiguous range of tiles; a
 // tile is CH * blockDim.x consecutive chunks of one instance: lane t walks
 // chunks first + t * CH + c for c < CH.
-template <int FMT, bool BATCH, int CH>
+// ONLY_LDS: compiled for whole-table-in-LDS placements alone (single scans
+// of small dictionaries): without the other placements' code the kernel
+// needs fewer registers and more waves fit.
+template <int FMT, bool BATCH, int CH, bool ONLY_LDS = false>
 __global__ __launch_bounds__(kMaxCountThreads) void k_count(
     Inst single, const Inst *__restrict__ insts, const TileDesc *__restrict__ tiles,
     uint32_t n_tiles, uint32_t chunk, uint32_t warm, uint32_t *__restrict__ cnt,
@@ -498,7 +520,11 @@ __global__ __launch_bounds__(kMaxCountThreads) void k_count(
         }
         ChunkOut co[CH];
         bool done = false;
-        if constexpr (FMT == AC_TEXT_2BIT) {
+        if constexpr (ONLY_LDS) {
+            walk_count<FMT, PL_LDS, CH>(UTable<PL_LDS>{gtab, hot, row}, txt, out_size, size_bytes,
+                                        fo, fos, tz, inv, chunk, warm, in, seg_state, seg_m, co);
+            done = true;
+        } else if constexpr (FMT == AC_TEXT_2BIT) {
             if (uniform(I.stride2)) {
                 walk_count2<CH>(gtab, txt, out_size, size_bytes, fo, uniform(I.fo2_bytes), fos, tz,
                                 inv, chunk, warm, in, seg_state, seg_m, co);
@@ -1530,8 +1556,9 @@ static int validate_text(const ac_dict *d, const void *text, uint64_t n, uint32_
 
 template <int FMT, bool BATCH, int CH>
 static int launch_count_ch(const Geom &g, const Inst &I, const Inst *insts,
-                           const TileDesc *tiles, const Workspace &w, hipStream_t st) {
-    auto kc = k_count<FMT, BATCH, CH>;
+                           const TileDesc *tiles, const Workspace &w, bool only_lds,
+                           hipStream_t st) {
+    auto kc = only_lds ? k_count<FMT, BATCH, CH, true> : k_count<FMT, BATCH, CH>;
     int rc = allow_lds(kc, g.lds_bytes);
     if (rc) return rc;
     KTimer tm(AC_K_COUNT, st);
@@ -1543,18 +1570,18 @@ static int launch_count_ch(const Geom &g, const Inst &I, const Inst *insts,
 
 template <int FMT, bool BATCH>
 static int launch_count(const Geom &g, const Inst &I, const Inst *insts, const TileDesc *tiles,
-                        const Workspace &w, hipStream_t st) {
+                        const Workspace &w, bool only_lds, hipStream_t st) {
     switch (g.chains) {
-        case 1: return launch_count_ch<FMT, BATCH, 1>(g, I, insts, tiles, w, st);
-        case 2: return launch_count_ch<FMT, BATCH, 2>(g, I, insts, tiles, w, st);
-        default: return launch_count_ch<FMT, BATCH, 4>(g, I, insts, tiles, w, st);
+        case 1: return launch_count_ch<FMT, BATCH, 1>(g, I, insts, tiles, w, only_lds, st);
+        case 2: return launch_count_ch<FMT, BATCH, 2>(g, I, insts, tiles, w, only_lds, st);
+        default: return launch_count_ch<FMT, BATCH, 4>(g, I, insts, tiles, w, only_lds, st);
     }
 }
 
 template <int FMT>
 static int launch_single(const Geom &g, const Inst &I, const Workspace &w, hipStream_t st) {
     const uint32_t T = (uint32_t)g.n_tiles;
-    int rc = launch_count<FMT, false>(g, I, nullptr, nullptr, w, st);
+    int rc = launch_count<FMT, false>(g, I, nullptr, nullptr, w, I.lds_all && !I.stride2, st);
     if (rc) return rc;
     {
         KTimer tm(AC_K_OFFSETS, st);
