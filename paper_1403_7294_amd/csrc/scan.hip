@@ -458,15 +458,16 @@ __device__ __forceinline__ void load_lds_table(rsrc_t g, uint32_t bytes) {
 template <int FMT, bool BATCH, int CH, bool ONLY_LDS = false>
 __global__ __launch_bounds__(kMaxCountThreads) void k_count(
     Inst single, const Inst *__restrict__ insts, const TileDesc *__restrict__ tiles,
-    uint32_t n_tiles, uint32_t chunk, uint32_t warm, uint32_t *__restrict__ cnt,
+    uint32_t t_base, uint32_t n_tiles, uint32_t chunk, uint32_t warm, uint32_t *__restrict__ cnt,
     uint32_t *__restrict__ mask, u32x4 *__restrict__ seg_state, uint32_t *__restrict__ seg_m,
     unsigned long long *__restrict__ tile_m, uint32_t *__restrict__ tile_zs,
     uint32_t *__restrict__ tile_zd) {
     __shared__ unsigned long long red_a[16];
     __shared__ uint32_t red_b[16], red_c[16];
     const uint32_t spc = chunk / kSeg;
-    const uint32_t t0 = (uint32_t)(((uint64_t)n_tiles * blockIdx.x) / gridDim.x);
-    const uint32_t t1 = (uint32_t)(((uint64_t)n_tiles * (blockIdx.x + 1)) / gridDim.x);
+    // this launch covers tiles t_base .. t_base + n_tiles - 1
+    const uint32_t t0 = t_base + (uint32_t)(((uint64_t)n_tiles * blockIdx.x) / gridDim.x);
+    const uint32_t t1 = t_base + (uint32_t)(((uint64_t)n_tiles * (blockIdx.x + 1)) / gridDim.x);
     int cur = -1;
     for (uint32_t t = t0; t < t1; ++t) {
         uint32_t inst = 0, first, count;
@@ -1557,31 +1558,41 @@ static int validate_text(const ac_dict *d, const void *text, uint64_t n, uint32_
 template <int FMT, bool BATCH, int CH>
 static int launch_count_ch(const Geom &g, const Inst &I, const Inst *insts,
                            const TileDesc *tiles, const Workspace &w, bool only_lds,
-                           hipStream_t st) {
+                           uint32_t t_base, uint32_t n_tiles, hipStream_t st) {
+    if (n_tiles == 0) return AC_OK;
     auto kc = only_lds ? k_count<FMT, BATCH, CH, true> : k_count<FMT, BATCH, CH>;
     int rc = allow_lds(kc, g.lds_bytes);
     if (rc) return rc;
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(n_tiles, g.grid_count);
     KTimer tm(AC_K_COUNT, st);
-    hipLaunchKernelGGL(kc, dim3(g.grid_count), dim3(g.threads), g.lds_bytes, st, I, insts, tiles,
-                       (uint32_t)g.n_tiles, g.chunk, g.warm, w.cnt, w.mask, w.seg_state, w.seg_m,
-                       w.tile_m, w.tile_zs, w.tile_zd);
+    hipLaunchKernelGGL(kc, dim3(grid), dim3(g.threads), g.lds_bytes, st, I, insts, tiles, t_base,
+                       n_tiles, g.chunk, g.warm, w.cnt, w.mask, w.seg_state, w.seg_m, w.tile_m,
+                       w.tile_zs, w.tile_zd);
     return AC_OK;
 }
 
 template <int FMT, bool BATCH>
 static int launch_count(const Geom &g, const Inst &I, const Inst *insts, const TileDesc *tiles,
-                        const Workspace &w, bool only_lds, hipStream_t st) {
+                        const Workspace &w, bool only_lds, uint32_t t_base, uint32_t n_tiles,
+                        hipStream_t st) {
     switch (g.chains) {
-        case 1: return launch_count_ch<FMT, BATCH, 1>(g, I, insts, tiles, w, only_lds, st);
-        case 2: return launch_count_ch<FMT, BATCH, 2>(g, I, insts, tiles, w, only_lds, st);
-        default: return launch_count_ch<FMT, BATCH, 4>(g, I, insts, tiles, w, only_lds, st);
+        case 1:
+            return launch_count_ch<FMT, BATCH, 1>(g, I, insts, tiles, w, only_lds, t_base, n_tiles,
+                                                  st);
+        case 2:
+            return launch_count_ch<FMT, BATCH, 2>(g, I, insts, tiles, w, only_lds, t_base, n_tiles,
+                                                  st);
+        default:
+            return launch_count_ch<FMT, BATCH, 4>(g, I, insts, tiles, w, only_lds, t_base, n_tiles,
+                                                  st);
     }
 }
 
 template <int FMT>
 static int launch_single(const Geom &g, const Inst &I, const Workspace &w, hipStream_t st) {
     const uint32_t T = (uint32_t)g.n_tiles;
-    int rc = launch_count<FMT, false>(g, I, nullptr, nullptr, w, I.lds_all && !I.stride2, st);
+    int rc = launch_count<FMT, false>(g, I, nullptr, nullptr, w, I.lds_all && !I.stride2, 0, T,
+                                      st);
     if (rc) return rc;
     {
         KTimer tm(AC_K_OFFSETS, st);
