@@ -155,11 +155,11 @@ __device__ __forceinline__ uint32_t lds_load_u16(uint32_t byte_addr) {
 //              LDS as 16-bit state ids, at half the byte address; an id of
 //              0xFFFF (a state too far down the numbering for 16 bits) and
 //              every other row are read from the 32-bit table.
-template <int PLACE>
+template <int PLACE, bool ROW16 = false>
 struct UTable {
     rsrc_t g;
     uint32_t hot;  // hybrid: first row offset not held in LDS
-    uint32_t row;  // hybrid: sigma * 4, bytes of a 32-bit row
+    uint32_t row;  // hybrid: sigma * 4, bytes of a 32-bit row (16 when ROW16)
     __device__ __forceinline__ uint32_t operator()(uint32_t a) const {
         if constexpr (PLACE == PL_LDS) {
             return lds_load(a);
@@ -176,7 +176,7 @@ struct UTable {
             const uint32_t h = lds_load_u16((in ? a : 0u) >> 1);
             const bool esc = in && h == 0xFFFFu;
             if (esc) v2 = buf_load(g, a);
-            return in ? (esc ? v2 : h * row) : v1;
+            return in ? (esc ? v2 : (ROW16 ? h << 4 : h * row)) : v1;
         }
     }
 };

@@ -116,8 +116,8 @@ struct ChainIn {
 // A word is walked with one lookup per symbol plus a running max; only a
 // word that reaches an output state adds output-set sizes (rare).  For each
 // segment with matches the entry state and the count are stored.
-template <int FMT, int PLACE, int CH>
-__device__ __forceinline__ void walk_count(const UTable<PLACE> &tab, const UText &txt,
+template <int FMT, int PLACE, int CH, bool ROW16 = false>
+__device__ __forceinline__ void walk_count(const UTable<PLACE, ROW16> &tab, const UText &txt,
                                            const uint32_t *__restrict__ out_size,
                                            uint32_t out_size_bytes, uint32_t fo,
                                            uint32_t fo_state, uint32_t tz, uint32_t inv,
@@ -541,9 +541,11 @@ __global__ __launch_bounds__(kMaxCountThreads) void k_count(
                                            size_bytes, fo, fos, tz, inv, chunk, warm, in,
                                            seg_state, seg_m, co);
         } else {
-            walk_count<FMT, PL_HYBRID, CH>(UTable<PL_HYBRID>{gtab, hot, row}, txt, out_size,
-                                           size_bytes, fo, fos, tz, inv, chunk, warm, in,
-                                           seg_state, seg_m, co);
+            // 2-bit text means sigma 4: a row is 16 bytes, an id becomes a
+            // row offset by a shift
+            walk_count<FMT, PL_HYBRID, CH, FMT == AC_TEXT_2BIT>(
+                UTable<PL_HYBRID, FMT == AC_TEXT_2BIT>{gtab, hot, row}, txt, out_size, size_bytes,
+                fo, fos, tz, inv, chunk, warm, in, seg_state, seg_m, co);
         }
         unsigned long long m = 0;
         uint32_t zs = 0, zd = 0;
