@@ -115,6 +115,13 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise LibraryMissing(
             f"{LIB_PATH} is not built; run `python -m paper_1403_7294_amd.build`")
+    # torch ships its own HIP runtime under the same soname as the system's;
+    # loading torch first makes the library bind to that one, so the process
+    # has a single HIP runtime whichever package touches the GPU first
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     P, u32, u64, i = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
     L.ac_build.argtypes = [P, P, u32, ctypes.POINTER(ac_build_opts), ctypes.POINTER(P)]

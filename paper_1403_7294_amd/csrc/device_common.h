@@ -169,12 +169,17 @@ struct UTable {
             // rows past the LDS part go to the cache hierarchy first, so
             // their latency overlaps the LDS read of the other lanes; a hot
             // row entry 0xFFFF (target id beyond 16 bits) is read again from
-            // the 32-bit table
+            // the 32-bit table.  Lanes that need no global read give the
+            // load an offset past the buffer's end: the load returns 0
+            // without a memory access, and the step stays straight-line
+            // code, so the loads of independent chains can be in flight
+            // together instead of each waiting behind an exec-mask branch.
+            constexpr uint32_t kNoRead = 0xFFFFFFF0u;
             const bool in = a < hot;
-            uint32_t v1 = 0, v2 = 0;
-            if (!in) v1 = buf_load(g, a);
+            const uint32_t v1 = buf_load(g, in ? kNoRead : a);
             const uint32_t h = lds_load_u16((in ? a : 0u) >> 1);
             const bool esc = in && h == 0xFFFFu;
+            uint32_t v2 = 0;
             if (esc) v2 = buf_load(g, a);
             return in ? (esc ? v2 : (ROW16 ? h << 4 : h * row)) : v1;
         }

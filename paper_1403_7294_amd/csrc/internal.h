@@ -68,6 +68,7 @@ struct ac_dict {
     uint32_t *d_out_off = nullptr;
     uint32_t *d_out_ids = nullptr;
     uint32_t *d_out_size = nullptr;  // |out(s)| per output state
+    uint32_t *d_delta_sz = nullptr;  // sigma 4: row offset | |out(target)| << 24 (count walk)
     uint16_t *d_hot16 = nullptr;  // first hot16_rows rows as 16-bit ids (0xFFFF: see table)
     uint32_t hot16_rows = 0;
     // sigma 4 only, when it fits LDS: transitions over two symbols,

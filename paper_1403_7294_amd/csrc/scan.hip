@@ -34,6 +34,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -65,6 +66,7 @@ struct Inst {
     const uint32_t *out_off;
     const uint32_t *out_ids;
     const uint32_t *out_size;  // |out(s)| per output state (count pass)
+    const uint32_t *delta_sz;  // sigma 4: count table (row offset | |out(target)| << 24)
     const uint16_t *hot16;   // 16-bit rows for the hybrid placement
     const uint8_t *text;
     ac_match *out;
@@ -283,6 +285,187 @@ __device__ __forceinline__ void walk_count(const UTable<PLACE, ROW16> &tab, cons
     }
 }
 
+// Count table for 2-bit text (sigma 4, 16-byte rows).  Its 32-bit entries
+// are the target's row offset (below 2^24) with |out(target)| in the top
+// byte, so the walk counts matches as it goes.  The 16-bit rows in LDS hold
+// the ids of output-free targets; 0xFFFF (an output state, or an id past 16
+// bits) means "read the 32-bit entry".  A lane on a row in LDS gives the
+// global load an offset past the buffer's end (value 0, no memory access);
+// a lane on any other row reads the LDS zero word just past the 16-bit rows
+// (byte hot / 2).  The next entry is then (h << 4) | v for every lane.
+constexpr uint32_t kRowBits = 0x00FFFFFFu;  // row offset part of a count-table entry
+
+struct HotTable16 {
+    rsrc_t g;      // count table
+    uint32_t hot;  // first row offset not in LDS
+    // One lookup for each of CH independent chains: every chain's global
+    // and LDS reads are issued before any result is used, and the rare
+    // escape is tested once for all chains, so the chains' latencies
+    // overlap inside the wave.
+    template <int CH>
+    __device__ __forceinline__ void step(const uint32_t (&a)[CH], uint32_t (&r)[CH]) const {
+        constexpr uint32_t kNoRead = 0xFFFFFFF0u;
+        // the 16-bit rows start at LDS address 0 (the count kernel has no
+        // static LDS; the host checks that before choosing this walk)
+        typedef __attribute__((address_space(3))) uint16_t lds_u16;
+        uint32_t v[CH], h[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) v[c] = buf_load(g, a[c] < hot ? kNoRead : a[c]);
+#pragma unroll
+        for (int c = 0; c < CH; ++c) h[c] = *(const lds_u16 *)(uintptr_t)(min(a[c], hot) >> 1);
+        bool esc = false;
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            r[c] = h[c] << 4 | v[c];
+            esc = esc || h[c] > 0xFFFEu;
+        }
+        if (esc) {
+#pragma unroll
+            for (int c = 0; c < CH; ++c)
+                if (h[c] > 0xFFFEu) r[c] = buf_load(g, a[c]);
+        }
+    }
+};
+
+// The count walk for 2-bit text against a HotTable16.  Rows are 16-byte
+// aligned, so a symbol's column is OR-ed into the row offset, and every
+// step adds the entered state's output-set size from the entry's top byte:
+// no per-word output test and no re-read of sizes.  Positions past the
+// chunk's text (only in the text's last word) are walked by a variant that
+// drops their counts.  One output event is kept per segment: a running max
+// of (entry | position in the word) lands on an output state whenever the
+// word has one (only those entries have a nonzero top byte), and a segment
+// whose count equals that state's set size has exactly one position with
+// output -- the common case for segments with few matches.  Other segments
+// are marked as having many events (the emit pass walks their quarters).
+template <int CH>
+__device__ __forceinline__ void walk_count_h16(const HotTable16 &tab, const UText &txt,
+                                               uint32_t fo, uint32_t chunk, uint32_t warm,
+                                               const ChainIn (&in)[CH],
+                                               u32x4 *__restrict__ seg_state,
+                                               uint32_t *__restrict__ seg_m, ChunkOut (&r)[CH]) {
+    constexpr uint32_t SPW = 16;          // bases per text word
+    constexpr uint32_t WPS = kSeg / SPW;  // words per segment (one per quarter)
+    static_assert(WPS == 4 && kQuarter == SPW, "a quarter segment is one text word");
+    const uint32_t wpc = chunk / SPW, spc = chunk / kSeg;
+    uint32_t s[CH], w0[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+        w0[c] = in[c].j * wpc;
+        s[c] = 0;
+        r[c] = ChunkOut{0, 0, 0};
+    }
+    for (uint32_t i = 0; i < warm; ++i) {
+        uint32_t x[CH];
+        bool live[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int w = (int)w0[c] - (int)warm + (int)i;
+            x[c] = txt.word(w);
+            live[c] = w >= 0;
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < SPW; ++k) {
+            uint32_t a[CH], ns[CH];
+#pragma unroll
+            for (int c = 0; c < CH; ++c) a[c] = __builtin_amdgcn_ubfe(x[c], 2 * k, 2) << 2 | s[c];
+            tab.step<CH>(a, ns);
+#pragma unroll
+            for (int c = 0; c < CH; ++c) s[c] = live[c] ? ns[c] & kRowBits : s[c];
+        }
+    }
+    // the next two segments' text (one 16-byte vector each) in flight
+    constexpr uint32_t PD = 2;
+    u32x4 nx[CH][PD];
+#pragma unroll
+    for (int c = 0; c < CH; ++c)
+#pragma unroll
+        for (uint32_t p = 0; p < PD; ++p)
+            nx[c][p] = p < spc ? txt.vec_once(w0[c] + WPS * p) : u32x4{0, 0, 0, 0};
+    for (uint32_t g = 0; g < spc; ++g) {
+        uint32_t qs[CH][4], sm[CH], he[CH], hq[CH];
+        u32x4 x4[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            sm[c] = 0;
+            he[c] = 0;  // an output entry | its position in the word (0: none yet)
+            hq[c] = 0;  // the word it was seen in
+            x4[c] = nx[c][0];
+            nx[c][0] = nx[c][1];
+            if (g + PD < spc) nx[c][1] = txt.vec_once(w0[c] + WPS * (g + PD));
+        }
+#pragma unroll
+        for (uint32_t q = 0; q < 4; ++q) {
+            const uint32_t p0 = (g * WPS + q) * SPW;
+            bool part = false;
+            uint32_t hw[CH];
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                qs[c][q] = s[c];
+                hw[c] = 0;
+                part = part || (in[c].lim != 0 && p0 + SPW > in[c].lim);
+            }
+            if (!part) {
+#pragma unroll
+                for (uint32_t k = 0; k < SPW; ++k) {
+                    uint32_t a[CH], ns[CH];
+#pragma unroll
+                    for (int c = 0; c < CH; ++c)
+                        a[c] = __builtin_amdgcn_ubfe(x4[c][q], 2 * k, 2) << 2 | s[c];
+                    tab.step<CH>(a, ns);
+#pragma unroll
+                    for (int c = 0; c < CH; ++c) {
+                        sm[c] += ns[c] >> 24;
+                        hw[c] = max(hw[c], ns[c] | k);
+                        s[c] = ns[c] & kRowBits;
+                    }
+                }
+            } else {
+                // the text ends inside (or before) this word
+#pragma unroll
+                for (uint32_t k = 0; k < SPW; ++k) {
+                    uint32_t a[CH], ns[CH];
+#pragma unroll
+                    for (int c = 0; c < CH; ++c)
+                        a[c] = __builtin_amdgcn_ubfe(x4[c][q], 2 * k, 2) << 2 | s[c];
+                    tab.step<CH>(a, ns);
+#pragma unroll
+                    for (int c = 0; c < CH; ++c) {
+                        const bool ok = p0 + k < in[c].lim;
+                        sm[c] += ok ? ns[c] >> 24 : 0u;
+                        hw[c] = ok ? max(hw[c], ns[c] | k) : hw[c];
+                        s[c] = ns[c] & kRowBits;
+                    }
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const bool hit = hw[c] > kRowBits;
+                he[c] = hit ? hw[c] : he[c];
+                hq[c] = hit ? q : hq[c];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            if (in[c].lim == 0) sm[c] = 0;  // a lane past the tile's last chunk
+            if (sm[c]) {
+                r[c].mask |= 1u << g;
+                u32x4 *rec = seg_state + 2 * (in[c].seg0 + g);
+                rec[0] = u32x4{qs[c][0], qs[c][1], qs[c][2], qs[c][3]};
+                // one position with output: its event (set index, position)
+                const bool one = sm[c] == he[c] >> 24;
+                const uint32_t o = (((he[c] & kRowBits) >> 4) - (fo >> 4));
+                rec[1] = u32x4{one && o <= kEvMaxSet ? o << 6 | hq[c] * SPW | (he[c] & 15u)
+                                                     : kEvMany,
+                               kEvNone, kEvNone, kEvNone};
+                seg_m[in[c].seg0 + g] = sm[c];
+                r[c].dense += sm[c] >= kDenseMatches;
+            }
+            r[c].m += sm[c];
+        }
+    }
+}
+
 // The same walk over 2-bit DNA with the two-symbol table in LDS: one lookup
 // per two bases.  An entry is the row offset of the state after both
 // symbols (state * 64) with bit 31 set when the state after the first symbol
@@ -452,18 +635,26 @@ __device__ __forceinline__ void load_lds_table(rsrc_t g, uint32_t bytes) {
 // Persistent count kernel.  Block b takes a contiguous range of tiles; a
 // tile is CH * blockDim.x consecutive chunks of one instance: lane t walks
 // chunks first + t * CH + c for c < CH.
-// ONLY_LDS: compiled for whole-table-in-LDS placements alone (single scans
-// of small dictionaries): without the other placements' code the kernel
-// needs fewer registers and more waves fit.
-template <int FMT, bool BATCH, int CH, bool ONLY_LDS = false>
+// MODE selects the placements the kernel is compiled for: kCountAny (all,
+// chosen per instance), kCountLds (whole table in LDS) or kCountHybrid (hot
+// rows in LDS, the rest from L2).  Without the other placements' code a
+// kernel needs fewer registers: more waves or more chains per lane fit.
+constexpr int kCountAny = 0, kCountLds = 1, kCountHybrid = 2;
+template <int FMT, bool BATCH, int CH, int MODE = kCountAny>
 __global__ __launch_bounds__(kMaxCountThreads) void k_count(
     Inst single, const Inst *__restrict__ insts, const TileDesc *__restrict__ tiles,
-    uint32_t t_base, uint32_t n_tiles, uint32_t chunk, uint32_t warm, uint32_t *__restrict__ cnt,
+    uint32_t t_base, uint32_t n_tiles, uint32_t chunk, uint32_t warm, uint32_t red_off,
+    uint32_t *__restrict__ cnt,
     uint32_t *__restrict__ mask, u32x4 *__restrict__ seg_state, uint32_t *__restrict__ seg_m,
     unsigned long long *__restrict__ tile_m, uint32_t *__restrict__ tile_zs,
     uint32_t *__restrict__ tile_zd) {
-    __shared__ unsigned long long red_a[16];
-    __shared__ uint32_t red_b[16], red_c[16];
+    // block reduction slots after the LDS table (the kernel has no static
+    // LDS, so the table starts at LDS address 0)
+    extern __shared__ uint32_t dyn_smem[];
+    typedef __attribute__((address_space(3))) unsigned long long lds_u64;
+    lds_u64 *red_a = (lds_u64 *)((lds_u8 *)(lds_u32 *)dyn_smem + red_off);
+    lds_u32 *red_b = (lds_u32 *)((lds_u8 *)(lds_u32 *)dyn_smem + red_off + 128u);
+    lds_u32 *red_c = red_b + 16;
     const uint32_t spc = chunk / kSeg;
     // this launch covers tiles t_base .. t_base + n_tiles - 1
     const uint32_t t0 = t_base + (uint32_t)(((uint64_t)n_tiles * blockIdx.x) / gridDim.x);
@@ -494,8 +685,8 @@ __global__ __launch_bounds__(kMaxCountThreads) void k_count(
                     load_lds_table(make_rsrc(uniform(I.delta2), lb), lb);
                 else if (lds_all)
                     load_lds_table(gtab, lb);
-                else
-                    load_lds_table(make_rsrc(uniform(I.hot16), lb), lb);
+                else  // 16-bit rows, then zeros up to lb
+                    load_lds_table(make_rsrc(uniform(I.hot16), ((hot >> 1) + 3u) & ~3u), lb);
                 __syncthreads();
             }
             cur = (int)inst;
@@ -521,9 +712,18 @@ __global__ __launch_bounds__(kMaxCountThreads) void k_count(
         }
         ChunkOut co[CH];
         bool done = false;
-        if constexpr (ONLY_LDS) {
+        if constexpr (MODE == kCountLds) {
             walk_count<FMT, PL_LDS, CH>(UTable<PL_LDS>{gtab, hot, row}, txt, out_size, size_bytes,
                                         fo, fos, tz, inv, chunk, warm, in, seg_state, seg_m, co);
+            done = true;
+        } else if constexpr (MODE == kCountHybrid) {
+            if constexpr (FMT == AC_TEXT_2BIT)
+                walk_count_h16<CH>(HotTable16{make_rsrc(uniform(I.delta_sz), table_bytes), hot},
+                                   txt, fo, chunk, warm, in, seg_state, seg_m, co);
+            else
+                walk_count<FMT, PL_HYBRID, CH>(UTable<PL_HYBRID>{gtab, hot, row}, txt, out_size,
+                                               size_bytes, fo, fos, tz, inv, chunk, warm, in,
+                                               seg_state, seg_m, co);
             done = true;
         } else if constexpr (FMT == AC_TEXT_2BIT) {
             if (uniform(I.stride2)) {
@@ -835,136 +1035,200 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
     }
 }
 
-// Dense part of the work list: one wave per listed segment.  Four groups of
-// 16 lanes walk the segment's four quarters at once, each from the state the
-// count pass stored for its quarter (16 dependent lookups per segment); lane
-// k keeps the state entered at position k and, before any store is issued,
-// loads where that state's output set starts and how long it is.  A prefix
-// sum over the wave gives every position its first slot.
+// Dense part of the work list.  A wave takes kDenseBatch listed segments at
+// once.  For each of them, four groups of 16 lanes walk the segment's four
+// quarters from the states the count pass stored (16 dependent lookups per
+// quarter); the segments' walks are independent chains, interleaved, so one
+// walk latency serves the whole batch.  Lane k of group g keeps the state
+// entered at position 16 g + k.  Only then are the batch's records written:
+// on gfx9 a wave's wait for a load also waits for its earlier stores, so
+// walking between the stores of consecutive segments would pay the store
+// drain and the walk latency per segment.
 //
-// The positions are then written as runs of equal states (a poly-A run is
-// one long run of the deepest all-A state): a run of r positions whose set
-// has L ids is r * L consecutive slots, item t of the run being id t % L at
-// end position first + t / L.  The wave writes the run item-parallel, lane i
-// taking items i, i + 64, ... (with a trip count uniform over the wave, so
-// no lane is inactive during a shuffle), so every store instruction covers 64
-// consecutive 8-byte slots; the run's ids sit in two registers per lane and
-// are picked with a wave shuffle (an LDS-path operation, which does not wait
-// for the wave's stores the way a memory load would).  Sets longer than 128
-// ids take a slower path that loads them per position.
+// A segment's positions are written as runs of equal states (a poly-A run
+// is one long run of the deepest all-A state): a run of r positions whose
+// set has L ids is r * L consecutive slots, item t of the run being id
+// t % L at end position first + t / L.  The wave writes the run
+// item-parallel, lane i taking items i, i + 64, ... (with a trip count
+// uniform over the wave, so no lane is inactive during a shuffle), so every
+// store instruction covers 64 consecutive 8-byte slots; the run's ids sit in
+// two registers per lane and are picked with a wave shuffle (an LDS-path
+// operation, which does not wait for the wave's stores the way a memory
+// load would).  Sets longer than 128 ids take a slower path that loads them
+// per position.
 constexpr uint32_t kDenseThreads = 256;
+constexpr uint32_t kDenseBatch = 4;
 
+// Records of one dense segment.  Lane l holds `mine`, the state entered at
+// position l, and (a, len), where its output set starts in the id array
+// and its size (len 0: no output, or past the text).
+__device__ __forceinline__ void dense_runs(uint32_t mine, uint32_t a, uint32_t len,
+                                           uint32_t lane, uint32_t e0, unsigned long long off0,
+                                           unsigned long long cap,
+                                           const uint32_t *__restrict__ ids,
+                                           ac_match *__restrict__ out) {
+    const bool has = len != 0;
+    const uint32_t excl = wave_incl_scan(len) - len;
+    // runs: a run starts at an output position whose predecessor is in a
+    // different state or has no output; it ends before the next start or
+    // the next position without output
+    const uint32_t prev = __shfl_up(mine, 1, 64);
+    const bool prev_has = __shfl_up((uint32_t)has, 1, 64) != 0;
+    const bool start = has && (lane == 0 || !prev_has || prev != mine);
+    uint64_t starts = __ballot(start);
+    const uint64_t stops = __ballot(start || !has);
+    while (starts) {
+        const uint32_t k = (uint32_t)__builtin_ctzll(starts);
+        starts &= starts - 1;
+        const uint64_t after = stops & ~((2ull << k) - 1ull);  // bits above k
+        const uint32_t kend = after ? (uint32_t)__builtin_ctzll(after) : 64u;
+        const uint32_t r = kend - k;
+        const uint32_t L = __builtin_amdgcn_readlane(len, k);
+        const uint32_t ka = __builtin_amdgcn_readlane(a, k);
+        const unsigned long long ko = off0 + __builtin_amdgcn_readlane(excl, k);
+        if (ko >= cap) break;
+        const uint32_t T = r * L;
+        const uint32_t e = e0 + k;
+        if (L <= 128) {
+            uint32_t v0 = 0, v1 = 0;
+            if (L <= 16) {
+                // wave-uniform reads through the scalar cache: they do not
+                // wait for this wave's earlier stores as a vector load would
+                // (indices past the set repeat its last id: never read past
+                // the array)
+#pragma unroll
+                for (uint32_t j = 0; j < 16; ++j) {
+                    const uint32_t x = ids[ka + min(j, L - 1)];
+                    v0 = lane == j ? x : v0;
+                }
+            } else {
+                v0 = lane < L ? ids[ka + lane] : 0u;
+                v1 = lane + 64 < L ? ids[ka + 64 + lane] : 0u;
+            }
+            // item t = lane + 64 u of the run is id t % L at position t / L;
+            // a step of 64 items moves the id index by dj and the position
+            // by di (64 = di * L + dj), plus one when the index wraps.  The
+            // index is kept as a byte address for the shuffle.
+            const uint32_t di = 64u / L, dj4 = (64u - di * L) * 4u, L4 = L * 4u;
+            uint32_t i = lane / L;
+            uint32_t ja = (lane - i * L) * 4u;
+            // items below lim fit the output (the capacity may cut the run)
+            const uint32_t lim = (uint32_t)min<unsigned long long>(T, cap - ko);
+            ac_match *const run = out + ko;
+            // uniform trip count: every lane takes part in each shuffle
+            for (uint32_t base = 0; base < T; base += 64) {
+                const uint32_t x0 = (uint32_t)__builtin_amdgcn_ds_bpermute((int)ja, (int)v0);
+                uint32_t id = x0;
+                if (L > 64) {
+                    const uint32_t x1 =
+                        (uint32_t)__builtin_amdgcn_ds_bpermute((int)(ja & 255u), (int)v1);
+                    id = ja < 256u ? x0 : x1;
+                }
+                if (base + lane < lim) {
+                    ac_match m;
+                    m.pattern_id = id;
+                    m.end_pos = e + i;
+                    run[base + lane] = m;
+                }
+                ja += dj4;
+                i += di;
+                if (ja >= L4) {
+                    ja -= L4;
+                    ++i;
+                }
+            }
+        } else {
+            for (uint32_t i = 0; i < r; ++i) {
+                for (uint32_t j = lane; j < L; j += 64) {
+                    const unsigned long long d = ko + (unsigned long long)i * L + j;
+                    if (d < cap) {
+                        ac_match m;
+                        m.pattern_id = ids[ka + j];
+                        m.end_pos = e + i;
+                        out[d] = m;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ids1 / out1: a single scan's id array and output, as separate kernel
+// arguments so that the compiler knows the stores never touch the ids and
+// reads a run's ids through the scalar cache (batches use each instance's).
 template <int FMT, bool BATCH>
 __global__ __launch_bounds__(kDenseThreads) void k_emit_dense(
     Inst single, const Inst *__restrict__ insts, const uint32_t *__restrict__ list_seg,
     const u32x4 *__restrict__ list_state, const unsigned long long *__restrict__ list_moff,
-    const uint32_t *__restrict__ list_inst, const unsigned long long *__restrict__ totals) {
+    const uint32_t *__restrict__ list_inst, const unsigned long long *__restrict__ totals,
+    const uint32_t *__restrict__ ids1, ac_match *__restrict__ out1) {
     constexpr uint32_t SPW = Fmt<FMT>::SPW;
     constexpr uint32_t WPS = kSeg / SPW;
     constexpr uint32_t WPQ = kQuarter / SPW;  // text words per quarter
+    constexpr uint32_t B = kDenseBatch;
     const uint32_t n_sparse = (uint32_t)totals[1];
     const uint32_t n_dense = (uint32_t)totals[2];
     const uint32_t lane = threadIdx.x & 63;
+    const uint32_t gq = lane / kQuarter;  // the quarter this lane's group walks
     const uint32_t waves = gridDim.x * (blockDim.x >> 6);
-    for (uint32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < n_dense;
-         w += waves) {
-        const uint32_t idx = n_sparse + w;
-        const uint32_t inst = BATCH ? uniform(list_inst[idx]) : 0u;
-        const Inst &I = BATCH ? insts[inst] : single;
-        const uint32_t seg = uniform(list_seg[idx]);
-        const u32x4 qs = list_state[idx];
-        const uint32_t gq = lane / kQuarter;  // the quarter this lane's group walks
-        const uint32_t q0 = uniform(qs.x), q1 = uniform(qs.y), q2 = uniform(qs.z),
-                       q3 = uniform(qs.w);
-        uint32_t s = gq == 0 ? q0 : gq == 1 ? q1 : gq == 2 ? q2 : q3;
-        const unsigned long long off0 = uniform(list_moff[idx]);
-        const uint32_t e0 = seg * kSeg;
-        const uint32_t lim = min(kSeg, uniform(I.n) - e0);
-        const uint32_t fo = uniform(I.fo_bytes), fos = uniform(I.fo_state);
-        const uint32_t tz = uniform(I.div_tz), inv = uniform(I.div_inv);
-        const uint32_t tb = uniform(I.table_bytes), tb4 = uniform(I.text_bytes4);
-        const uint32_t *out_off = uniform(I.out_off);
-        const uint32_t *ids = uniform(I.out_ids);
-        ac_match *out = uniform(I.out);
-        const unsigned long long cap = uniform(I.capacity);
-        if (off0 >= cap) continue;
-        const UTable<PL_GLOBAL> tab{make_rsrc(uniform(I.delta), tb), 0, 0};
-        const UText txt{make_rsrc(uniform(I.text), tb4), tb4};
-        // four groups of 16 lanes walk the four quarters at once; lane
-        // 16 g + k keeps the state entered at position k of quarter g
-        uint32_t mine = 0;
+    for (uint32_t w = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * B; w < n_dense;
+         w += waves * B) {
+        uint32_t idx[B], seg[B], s[B], mine[B];
+        UTable<PL_GLOBAL> tab[B];
+        UText txt[B];
 #pragma unroll
-        for (uint32_t w = 0; w < WPQ; ++w) {
-            const uint32_t x = txt.word((int)(seg * WPS + gq * WPQ + w));
+        for (uint32_t b = 0; b < B; ++b) {
+            // past the list's end a slot walks the batch's first segment again
+            // and writes nothing
+            idx[b] = n_sparse + (w + b < n_dense ? w + b : w);
+            const Inst &I = BATCH ? insts[uniform(list_inst[idx[b]])] : single;
+            seg[b] = uniform(list_seg[idx[b]]);
+            const u32x4 qs = list_state[idx[b]];
+            s[b] = gq == 0 ? uniform(qs.x) : gq == 1 ? uniform(qs.y) : gq == 2 ? uniform(qs.z)
+                                                                    : uniform(qs.w);
+            mine[b] = 0;
+            const uint32_t tb4 = uniform(I.text_bytes4);
+            tab[b] = UTable<PL_GLOBAL>{make_rsrc(uniform(I.delta), uniform(I.table_bytes)), 0, 0};
+            txt[b] = UText{make_rsrc(uniform(I.text), tb4), tb4};
+        }
+#pragma unroll
+        for (uint32_t wq = 0; wq < WPQ; ++wq) {
+            uint32_t x[B];
+#pragma unroll
+            for (uint32_t b = 0; b < B; ++b) x[b] = txt[b].word((int)(seg[b] * WPS + gq * WPQ + wq));
 #pragma unroll
             for (uint32_t k = 0; k < SPW; ++k) {
-                s = tab(s + sym_bytes<FMT>(x, k));
-                if (lane % kQuarter == w * SPW + k) mine = s;
-            }
-        }
-        const bool has = mine >= fo && lane < lim;
-        uint32_t a = 0, len = 0;
-        if (has) {
-            const uint32_t o = row_state(mine, tz, inv) - fos;
-            a = out_off[o];
-            len = out_off[o + 1] - a;
-        }
-        const uint32_t excl = wave_incl_scan(len) - len;
-        // runs: a run starts at an output position whose predecessor is in a
-        // different state or has no output; it ends before the next start or
-        // the next position without output
-        const uint32_t prev = __shfl_up(mine, 1, 64);
-        const bool prev_has = __shfl_up((uint32_t)has, 1, 64) != 0;
-        const bool start = has && (lane == 0 || !prev_has || prev != mine);
-        uint64_t starts = __ballot(start);
-        const uint64_t stops = __ballot(start || !has);
-        while (starts) {
-            const uint32_t k = (uint32_t)__builtin_ctzll(starts);
-            starts &= starts - 1;
-            const uint64_t after = stops & ~((2ull << k) - 1ull);  // bits above k
-            const uint32_t kend = after ? (uint32_t)__builtin_ctzll(after) : 64u;
-            const uint32_t r = kend - k;
-            const uint32_t L = __builtin_amdgcn_readlane(len, k);
-            const uint32_t ka = __builtin_amdgcn_readlane(a, k);
-            const unsigned long long ko = off0 + __builtin_amdgcn_readlane(excl, k);
-            if (ko >= cap) break;
-            const uint32_t T = r * L;
-            const uint32_t e = e0 + k;
-            if (L <= 128) {
-                const uint32_t v0 = lane < L ? ids[ka + lane] : 0u;
-                const uint32_t v1 = lane + 64 < L ? ids[ka + 64 + lane] : 0u;
-                const float rcp = 1.0f / (float)L;
-                const bool all_in = ko + T <= cap;
-                // uniform trip count: every lane takes part in each shuffle
-#pragma unroll 2
-                for (uint32_t base = 0; base < T; base += 64) {
-                    const uint32_t t = base + lane;
-                    uint32_t i = (uint32_t)((float)t * rcp);
-                    if (i * L > t) --i;
-                    else if ((i + 1) * L <= t) ++i;
-                    const uint32_t j = t - i * L;
-                    const uint32_t x0 = (uint32_t)__shfl(v0, j & 63, 64);
-                    const uint32_t x1 = (uint32_t)__shfl(v1, j & 63, 64);
-                    if (t < T && (all_in || ko + t < cap)) {
-                        ac_match m;
-                        m.pattern_id = j < 64 ? x0 : x1;
-                        m.end_pos = e + i;
-                        out[ko + t] = m;
-                    }
-                }
-            } else {
-                for (uint32_t i = 0; i < r; ++i) {
-                    for (uint32_t j = lane; j < L; j += 64) {
-                        const unsigned long long d = ko + (unsigned long long)i * L + j;
-                        if (d < cap) {
-                            ac_match m;
-                            m.pattern_id = ids[ka + j];
-                            m.end_pos = e + i;
-                            out[d] = m;
-                        }
-                    }
+#pragma unroll
+                for (uint32_t b = 0; b < B; ++b) {
+                    s[b] = tab[b](s[b] + sym_bytes<FMT>(x[b], k));
+                    if (lane % kQuarter == wq * SPW + k) mine[b] = s[b];
                 }
             }
+        }
+        // where each position's output set starts and its size, for the
+        // whole batch before the first store
+        uint32_t a[B], len[B];
+#pragma unroll
+        for (uint32_t b = 0; b < B; ++b) {
+            const Inst &I = BATCH ? insts[uniform(list_inst[idx[b]])] : single;
+            const uint32_t e0 = seg[b] * kSeg;
+            const bool has = mine[b] >= uniform(I.fo_bytes) && lane < uniform(I.n) - e0;
+            const uint32_t o = has ? row_state(mine[b], uniform(I.div_tz), uniform(I.div_inv)) -
+                                         uniform(I.fo_state)
+                                   : 0u;
+            const uint32_t *out_off = uniform(I.out_off);
+            a[b] = has ? out_off[o] : 0u;
+            len[b] = has ? out_off[o + 1] : 0u;
+        }
+#pragma unroll
+        for (uint32_t b = 0; b < B; ++b) {
+            if (w + b >= n_dense) break;
+            const Inst &I = BATCH ? insts[uniform(list_inst[idx[b]])] : single;
+            const unsigned long long off0 = uniform(list_moff[idx[b]]);
+            const unsigned long long cap = uniform(I.capacity);
+            if (off0 >= cap) continue;
+            dense_runs(mine[b], a[b], len[b] - a[b], lane, seg[b] * kSeg, off0, cap,
+                       BATCH ? uniform(I.out_ids) : ids1, BATCH ? uniform(I.out) : out1);
         }
     }
 }
@@ -1205,7 +1469,8 @@ int upload_dict(ac_dict *d) {
     // (+2 entries: the LDS copy reads whole 32-bit words)
     std::vector<uint16_t> hot16((size_t)std::max<uint32_t>(hot_rows, 1) * T.sigma + 2, 0);
     for (size_t i = 0; i < (size_t)hot_rows * T.sigma; ++i)
-        hot16[i] = T.delta[i] < 0xFFFFu ? (uint16_t)T.delta[i] : (uint16_t)0xFFFFu;
+        hot16[i] = T.delta[i] < 0xFFFFu && T.delta[i] < T.first_output ? (uint16_t)T.delta[i]
+                                                                        : (uint16_t)0xFFFFu;
     d->hot16_rows = hot_rows;
     // two-symbol table, when it fits the count kernel's LDS
     std::vector<uint32_t> d2;
@@ -1235,12 +1500,24 @@ int upload_dict(ac_dict *d) {
     const size_t off_bytes = T.out_off.size() * 4;
     std::vector<uint32_t> sizes(std::max<size_t>(1, T.out_off.size() - 1), 0);
     for (size_t i = 0; i + 1 < T.out_off.size(); ++i) sizes[i] = T.out_off[i + 1] - T.out_off[i];
+    // sigma 4: the count table, row offset | |out(target)| << 24, when row
+    // offsets fit 24 bits and set sizes 8 bits
+    std::vector<uint32_t> dsz;
+    if (T.sigma == 4 && rows.size() * 4 <= kRowBits + 1ull && T.max_output <= 255) {
+        dsz.resize(rows.size());
+        for (size_t i = 0; i < rows.size(); ++i) {
+            const uint32_t t = T.delta[i];
+            const uint32_t n = t >= T.first_output ? sizes[t - T.first_output] : 0u;
+            dsz[i] = rows[i] | n << 24;
+        }
+    }
     const size_t ids_bytes = std::max<size_t>(4, T.out_ids.size() * 4);
     if (hipMalloc((void **)&d->d_delta, rows.size() * 4) != hipSuccess ||
         hipMalloc((void **)&d->d_out_off, off_bytes) != hipSuccess ||
         hipMalloc((void **)&d->d_out_ids, ids_bytes) != hipSuccess ||
         hipMalloc((void **)&d->d_out_size, sizes.size() * 4) != hipSuccess ||
         hipMalloc((void **)&d->d_hot16, hot16.size() * 2) != hipSuccess ||
+        (!dsz.empty() && hipMalloc((void **)&d->d_delta_sz, dsz.size() * 4) != hipSuccess) ||
         (!d2.empty() && hipMalloc((void **)&d->d_delta2, d2.size() * 4) != hipSuccess) ||
         (!go.empty() && (hipMalloc((void **)&d->d_go, go.size() * 4) != hipSuccess ||
                          hipMalloc((void **)&d->d_own_off, T.own_off.size() * 4) != hipSuccess ||
@@ -1258,6 +1535,9 @@ int upload_dict(ac_dict *d) {
              hipSuccess) ||
         hipMemcpy(d->d_hot16, hot16.data(), hot16.size() * 2, hipMemcpyHostToDevice) !=
             hipSuccess ||
+        (!dsz.empty() &&
+         hipMemcpy(d->d_delta_sz, dsz.data(), dsz.size() * 4, hipMemcpyHostToDevice) !=
+             hipSuccess) ||
         (!d2.empty() &&
          hipMemcpy(d->d_delta2, d2.data(), d2.size() * 4, hipMemcpyHostToDevice) != hipSuccess) ||
         (!go.empty() &&
@@ -1282,6 +1562,8 @@ void release_dict(ac_dict *d) {
     if (d->d_out_size) (void)hipFree(d->d_out_size);
     d->d_out_size = nullptr;
     if (d->d_hot16) (void)hipFree(d->d_hot16);
+    if (d->d_delta_sz) (void)hipFree(d->d_delta_sz);
+    d->d_delta_sz = nullptr;
     if (d->d_delta2) (void)hipFree(d->d_delta2);
     if (d->d_go) (void)hipFree(d->d_go);
     if (d->d_own_off) (void)hipFree(d->d_own_off);
@@ -1433,10 +1715,11 @@ static Placement choose_placement(const ac_dict *d, uint32_t requested, uint32_t
         pl.lds_all = 1;
         pl.lds_bytes = tb + kLdsPad;
     } else if (p == AC_PLACE_HYBRID) {
-        uint32_t rows = std::min<uint32_t>(d->hot16_rows, lds_limit / (sigma * 2u));
+        // the 16-bit rows, then one zero word (read by lanes on other rows)
+        uint32_t rows = std::min<uint32_t>(d->hot16_rows, (lds_limit - 8u) / (sigma * 2u));
         if (d->hot_states) rows = std::min(rows, d->hot_states);
         pl.hot = rows * sigma * 4u;
-        pl.lds_bytes = (rows * sigma * 2u + 3u) & ~3u;
+        pl.lds_bytes = ((rows * sigma * 2u + 3u) & ~3u) + 4u;
         if (rows == 0) pl = Placement{};
     }
     return pl;
@@ -1463,9 +1746,17 @@ static int resolve_geom(const ac_dict *const *dicts, const uint64_t *ns, uint32_
     g->warm = (max_len - 1 + spw - 1) / spw;
     g->threads = (tune && tune->block_threads) ? tune->block_threads : 1024u;
     if (g->threads < 64 || g->threads > kMaxCountThreads || g->threads % 64) return AC_E_INVALID;
-    // one chain per lane by default: with the output events the count walk
-    // keeps per segment, two chains need about 120 VGPRs and gain nothing
-    g->chains = (tune && tune->chains) ? tune->chains : 1u;
+    // chains per lane: one by default; a single 2-bit scan in the hybrid
+    // placement walks two at once (its walk keeps few registers, and two
+    // independent chains overlap their L2 latencies)
+    g->chains = 1;
+    if (tune && tune->chains) {
+        g->chains = tune->chains;
+    } else if (n_inst == 1 && fmt == AC_TEXT_2BIT && dicts[0]->d_delta_sz) {
+        const Placement pl =
+            choose_placement(dicts[0], tune ? tune->placement : 0, lds_limit, fmt);
+        if (pl.hot && !pl.lds_all && !pl.stride2) g->chains = 2;
+    }
     if (g->chains != 1 && g->chains != 2 && g->chains != 4) return AC_E_INVALID;
     const uint32_t per_tile = g->threads * g->chains;  // chunks per tile
     uint32_t chunk = tune ? tune->chunk : 0;
@@ -1515,6 +1806,7 @@ static void fill_inst(const ac_dict *d, const void *text, uint64_t n, uint32_t f
     I->out_off = d->d_out_off;
     I->out_ids = d->d_out_ids;
     I->out_size = d->d_out_size;
+    I->delta_sz = d->d_delta_sz;
     I->text = (const uint8_t *)text;
     I->out = out;
     I->count = (unsigned long long *)count;
@@ -1547,6 +1839,34 @@ static int allow_lds(K kernel, uint32_t bytes) {
     return AC_OK;
 }
 
+// Blocks of a persistent grid: no more than the device keeps resident at
+// once.  A block that could start only after others finish would run its
+// share of the work as a second, partial round.
+template <typename K>
+static uint32_t resident_grid(K kernel, uint32_t threads, uint32_t want) {
+    static std::mutex mu;
+    static std::map<const void *, int> per_cu;
+    int n = 0;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = per_cu.find((const void *)kernel);
+        if (it != per_cu.end()) n = it->second;
+    }
+    if (n == 0) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)kernel, (int)threads,
+                                                         0) != hipSuccess ||
+            n <= 0) {
+            (void)hipGetLastError();
+            n = 1;
+        }
+        std::lock_guard<std::mutex> lk(mu);
+        per_cu[(const void *)kernel] = n;
+    }
+    uint32_t cus = 1;
+    if (device_limits(&cus, nullptr) != AC_OK) cus = 1;
+    return std::max<uint32_t>(1, std::min<uint64_t>(want, (uint64_t)cus * (uint32_t)n));
+}
+
 static const uint64_t kMaxText = (1ull << 32) - 256;
 
 static int validate_text(const ac_dict *d, const void *text, uint64_t n, uint32_t fmt) {
@@ -1559,33 +1879,46 @@ static int validate_text(const ac_dict *d, const void *text, uint64_t n, uint32_
 
 template <int FMT, bool BATCH, int CH>
 static int launch_count_ch(const Geom &g, const Inst &I, const Inst *insts,
-                           const TileDesc *tiles, const Workspace &w, bool only_lds,
+                           const TileDesc *tiles, const Workspace &w, int mode,
                            uint32_t t_base, uint32_t n_tiles, hipStream_t st) {
     if (n_tiles == 0) return AC_OK;
-    auto kc = only_lds ? k_count<FMT, BATCH, CH, true> : k_count<FMT, BATCH, CH>;
-    int rc = allow_lds(kc, g.lds_bytes);
+    auto kc = k_count<FMT, BATCH, CH, kCountAny>;
+    if (mode == kCountLds) kc = k_count<FMT, BATCH, CH, kCountLds>;
+    // the hybrid-only kernel serves single scans (a batch mixes placements)
+    if constexpr (!BATCH)
+        if (mode == kCountHybrid) {
+            kc = k_count<FMT, BATCH, CH, kCountHybrid>;
+            // its 2-bit walk addresses the LDS rows from address 0: no static LDS
+            hipFuncAttributes fa;
+            if (hipFuncGetAttributes(&fa, (const void *)kc) != hipSuccess || fa.sharedSizeBytes)
+                return AC_E_HIP;
+        }
+    // the table, then the block reduction slots (16 u64 + 32 u32)
+    const uint32_t red_off = (g.lds_bytes + 7u) & ~7u;
+    const uint32_t dyn = red_off + 256u;
+    int rc = allow_lds(kc, dyn);
     if (rc) return rc;
     const uint32_t grid = (uint32_t)std::min<uint64_t>(n_tiles, g.grid_count);
     KTimer tm(AC_K_COUNT, st);
-    hipLaunchKernelGGL(kc, dim3(grid), dim3(g.threads), g.lds_bytes, st, I, insts, tiles, t_base,
-                       n_tiles, g.chunk, g.warm, w.cnt, w.mask, w.seg_state, w.seg_m, w.tile_m,
+    hipLaunchKernelGGL(kc, dim3(grid), dim3(g.threads), dyn, st, I, insts, tiles, t_base,
+                       n_tiles, g.chunk, g.warm, red_off, w.cnt, w.mask, w.seg_state, w.seg_m, w.tile_m,
                        w.tile_zs, w.tile_zd);
     return AC_OK;
 }
 
 template <int FMT, bool BATCH>
 static int launch_count(const Geom &g, const Inst &I, const Inst *insts, const TileDesc *tiles,
-                        const Workspace &w, bool only_lds, uint32_t t_base, uint32_t n_tiles,
+                        const Workspace &w, int mode, uint32_t t_base, uint32_t n_tiles,
                         hipStream_t st) {
     switch (g.chains) {
         case 1:
-            return launch_count_ch<FMT, BATCH, 1>(g, I, insts, tiles, w, only_lds, t_base, n_tiles,
+            return launch_count_ch<FMT, BATCH, 1>(g, I, insts, tiles, w, mode, t_base, n_tiles,
                                                   st);
         case 2:
-            return launch_count_ch<FMT, BATCH, 2>(g, I, insts, tiles, w, only_lds, t_base, n_tiles,
+            return launch_count_ch<FMT, BATCH, 2>(g, I, insts, tiles, w, mode, t_base, n_tiles,
                                                   st);
         default:
-            return launch_count_ch<FMT, BATCH, 4>(g, I, insts, tiles, w, only_lds, t_base, n_tiles,
+            return launch_count_ch<FMT, BATCH, 4>(g, I, insts, tiles, w, mode, t_base, n_tiles,
                                                   st);
     }
 }
@@ -1593,8 +1926,14 @@ static int launch_count(const Geom &g, const Inst &I, const Inst *insts, const T
 template <int FMT>
 static int launch_single(const Geom &g, const Inst &I, const Workspace &w, hipStream_t st) {
     const uint32_t T = (uint32_t)g.n_tiles;
-    int rc = launch_count<FMT, false>(g, I, nullptr, nullptr, w, I.lds_all && !I.stride2, 0, T,
-                                      st);
+    // the 2-bit hybrid walk reads the count table (built when it fits 24-bit
+    // row offsets and 8-bit set sizes)
+    const bool hyb_ok = FMT != AC_TEXT_2BIT || I.delta_sz;
+    const int mode = I.stride2              ? kCountAny
+                     : I.lds_all            ? kCountLds
+                     : I.hot_bytes && hyb_ok ? kCountHybrid
+                                            : kCountAny;
+    int rc = launch_count<FMT, false>(g, I, nullptr, nullptr, w, mode, 0, T, st);
     if (rc) return rc;
     {
         KTimer tm(AC_K_OFFSETS, st);
@@ -1611,15 +1950,20 @@ static int launch_single(const Geom &g, const Inst &I, const Workspace &w, hipSt
     }
     {
         KTimer tm(AC_K_EMIT, st);
-        hipLaunchKernelGGL((k_emit<FMT, false>), dim3(g.grid_emit), dim3(kEmitThreads), 0, st, I,
+        hipLaunchKernelGGL((k_emit<FMT, false>),
+                           dim3(resident_grid(k_emit<FMT, false>, kEmitThreads, g.grid_emit)),
+                           dim3(kEmitThreads), 0, st, I,
                            nullptr, w.list_seg, w.list_state, w.list_moff, nullptr, w.totals,
                            w.seg_state, g.chunk / kSeg);
     }
     {
         KTimer tm(AC_K_EMIT_DENSE, st);
-        hipLaunchKernelGGL((k_emit_dense<FMT, false>), dim3(g.grid_dense), dim3(kDenseThreads), 0,
+        hipLaunchKernelGGL((k_emit_dense<FMT, false>),
+                           dim3(resident_grid(k_emit_dense<FMT, false>, kDenseThreads,
+                                              g.grid_dense)),
+                           dim3(kDenseThreads), 0,
                            st, I, nullptr, w.list_seg, w.list_state, w.list_moff, nullptr,
-                           w.totals);
+                           w.totals, I.out_ids, I.out);
     }
     HIP_OK(hipGetLastError());
     return AC_OK;
