@@ -67,6 +67,7 @@ struct Inst {
     const uint32_t *out_ids;
     const uint32_t *out_size;  // |out(s)| per output state (count pass)
     const uint32_t *delta_sz;  // sigma 4: count table (row offset | |out(target)| << 24)
+    uint32_t n_ids;            // entries of out_ids
     const uint16_t *hot16;   // 16-bit rows for the hybrid placement
     const uint8_t *text;
     ac_match *out;
@@ -612,7 +613,7 @@ __device__ __forceinline__ void walk_count2(rsrc_t g1, const UText &txt,
 // Copy the LDS part of a table (zero-filled past the table's end).  Each
 // thread has 16 dword loads in flight before its first LDS write, so a
 // 160 KB table takes a few memory latencies rather than one per 4 KB.
-__device__ __forceinline__ void load_lds_table(rsrc_t g, uint32_t bytes) {
+__device__ __forceinline__ void load_lds_table(rsrc_t g, uint32_t bytes, uint32_t lds_off = 0) {
     extern __shared__ uint32_t dyn_smem[];
     constexpr uint32_t U = 4;
     const uint32_t step = blockDim.x * 16u;
@@ -627,7 +628,7 @@ __device__ __forceinline__ void load_lds_table(rsrc_t g, uint32_t bytes) {
 #pragma unroll
             for (uint32_t i = 0; i < 4; ++i) {
                 const uint32_t o = base + u * step + 4u * i;
-                if (o < bytes) ((lds_u32 *)dyn_smem)[o >> 2] = v[u][i];
+                if (o < bytes) ((lds_u32 *)dyn_smem)[(lds_off + o) >> 2] = v[u][i];
             }
     }
 }
@@ -1233,6 +1234,159 @@ __global__ __launch_bounds__(kDenseThreads) void k_emit_dense(
     }
 }
 
+// Dense emit of a single scan whose output-set tables fit LDS (set offsets,
+// then ids): each block copies them into LDS once, and a run then reads its
+// ids with LDS loads -- which, unlike memory loads, do not wait for the
+// wave's earlier stores -- with no per-run shuffle setup, for sets of any
+// size.  Walks, batching and the order of the records are those of
+// k_emit_dense.
+constexpr uint32_t kDenseLdsThreads = 1024;
+
+__device__ __forceinline__ void dense_runs_lds(uint32_t mine, uint32_t a, uint32_t len,
+                                               uint32_t lane, uint32_t e0,
+                                               unsigned long long off0, unsigned long long cap,
+                                               uint32_t ids_lds, ac_match *__restrict__ out) {
+    const bool has = len != 0;
+    const uint32_t excl = wave_incl_scan(len) - len;
+    const uint32_t prev = __shfl_up(mine, 1, 64);
+    const bool prev_has = __shfl_up((uint32_t)has, 1, 64) != 0;
+    const bool start = has && (lane == 0 || !prev_has || prev != mine);
+    uint64_t starts = __ballot(start);
+    const uint64_t stops = __ballot(start || !has);
+    while (starts) {
+        const uint32_t k = (uint32_t)__builtin_ctzll(starts);
+        starts &= starts - 1;
+        const uint64_t after = stops & ~((2ull << k) - 1ull);  // bits above k
+        const uint32_t kend = after ? (uint32_t)__builtin_ctzll(after) : 64u;
+        const uint32_t r = kend - k;
+        const uint32_t L = __builtin_amdgcn_readlane(len, k);
+        const uint32_t ka = __builtin_amdgcn_readlane(a, k);
+        const unsigned long long ko = off0 + __builtin_amdgcn_readlane(excl, k);
+        if (ko >= cap) break;
+        const uint32_t T = r * L;
+        const uint32_t e = e0 + k;
+        // item t = lane + 64 u is id t % L at position t / L; a step of 64
+        // items moves the id by dj and the position by di, plus one when
+        // the id index wraps.  The id is kept as its LDS byte address.
+        const uint32_t di = 64u / L, dj4 = (64u - di * L) * 4u;
+        uint32_t i = lane / L;
+        const uint32_t lo = ids_lds + ka * 4u, hi = lo + L * 4u;
+        uint32_t ja = lo + (lane - i * L) * 4u;
+        // items below lim fit the output (the capacity may cut the run);
+        // whole steps of 64 first, unchecked, then the partial one
+        const uint32_t lim = (uint32_t)min<unsigned long long>(T, cap - ko);
+        ac_match *run = out + ko + lane;
+        uint32_t base = 0;
+        auto step = [&]() {
+            ja += dj4;
+            i += di;
+            if (ja >= hi) {
+                ja -= L * 4u;
+                ++i;
+            }
+        };
+        // four steps at a time: their LDS reads are in flight together
+        for (; base + 256 <= lim; base += 256) {
+            uint32_t id[4], pos[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                id[u] = lds_load(ja);
+                pos[u] = e + i;
+                step();
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                ac_match m;
+                m.pattern_id = id[u];
+                m.end_pos = pos[u];
+                run[64 * u] = m;
+            }
+            run += 256;
+        }
+        for (; base + 64 <= lim; base += 64) {
+            ac_match m;
+            m.pattern_id = lds_load(ja);
+            m.end_pos = e + i;
+            *run = m;
+            run += 64;
+            step();
+        }
+        if (base + lane < lim) {
+            ac_match m;
+            m.pattern_id = lds_load(ja);
+            m.end_pos = e + i;
+            *run = m;
+        }
+    }
+}
+
+template <int FMT>
+__global__ __launch_bounds__(kDenseLdsThreads) void k_emit_dense_lds(
+    Inst I, const uint32_t *__restrict__ list_seg, const u32x4 *__restrict__ list_state,
+    const unsigned long long *__restrict__ list_moff, const unsigned long long *__restrict__ totals,
+    uint32_t off_bytes, uint32_t ids_bytes, ac_match *__restrict__ out) {
+    constexpr uint32_t SPW = Fmt<FMT>::SPW;
+    constexpr uint32_t WPS = kSeg / SPW;
+    constexpr uint32_t WPQ = kQuarter / SPW;
+    constexpr uint32_t B = kDenseBatch;
+    const uint32_t n_sparse = (uint32_t)totals[1];
+    const uint32_t n_dense = (uint32_t)totals[2];
+    // set offsets at LDS 0, ids after them
+    const uint32_t ids_lds = (off_bytes + 15u) & ~15u;
+    load_lds_table(make_rsrc(uniform(I.out_off), off_bytes), off_bytes);
+    load_lds_table(make_rsrc(uniform(I.out_ids), ids_bytes), ids_bytes, ids_lds);
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t gq = lane / kQuarter;
+    const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+    const UTable<PL_GLOBAL> tab{make_rsrc(uniform(I.delta), uniform(I.table_bytes)), 0, 0};
+    const uint32_t tb4 = uniform(I.text_bytes4);
+    const UText txt{make_rsrc(uniform(I.text), tb4), tb4};
+    const uint32_t fo = uniform(I.fo_bytes), fos = uniform(I.fo_state);
+    const uint32_t tz = uniform(I.div_tz), inv = uniform(I.div_inv);
+    const uint32_t n = uniform(I.n);
+    const unsigned long long cap = uniform(I.capacity);
+    for (uint32_t w = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * B; w < n_dense;
+         w += waves * B) {
+        uint32_t idx[B], seg[B], s[B], mine[B];
+#pragma unroll
+        for (uint32_t b = 0; b < B; ++b) {
+            idx[b] = n_sparse + (w + b < n_dense ? w + b : w);
+            seg[b] = uniform(list_seg[idx[b]]);
+            const u32x4 qs = list_state[idx[b]];
+            s[b] = gq == 0 ? uniform(qs.x) : gq == 1 ? uniform(qs.y) : gq == 2 ? uniform(qs.z)
+                                                                    : uniform(qs.w);
+            mine[b] = 0;
+        }
+#pragma unroll
+        for (uint32_t wq = 0; wq < WPQ; ++wq) {
+            uint32_t x[B];
+#pragma unroll
+            for (uint32_t b = 0; b < B; ++b) x[b] = txt.word((int)(seg[b] * WPS + gq * WPQ + wq));
+#pragma unroll
+            for (uint32_t k = 0; k < SPW; ++k) {
+#pragma unroll
+                for (uint32_t b = 0; b < B; ++b) {
+                    s[b] = tab(s[b] + sym_bytes<FMT>(x[b], k));
+                    if (lane % kQuarter == wq * SPW + k) mine[b] = s[b];
+                }
+            }
+        }
+#pragma unroll
+        for (uint32_t b = 0; b < B; ++b) {
+            if (w + b >= n_dense) break;
+            const unsigned long long off0 = uniform(list_moff[idx[b]]);
+            if (off0 >= cap) continue;
+            const uint32_t e0 = seg[b] * kSeg;
+            const bool has = mine[b] >= fo && lane < n - e0;
+            const uint32_t o = has ? row_state(mine[b], tz, inv) - fos : 0u;
+            const uint32_t a = has ? lds_load(o * 4u) : 0u;
+            const uint32_t len = has ? lds_load(o * 4u + 4u) - a : 0u;
+            dense_runs_lds(mine[b], a, len, lane, e0, off0, cap, ids_lds, out);
+        }
+    }
+}
+
 // ------------------------------------------------------------------ encode
 
 // Letters -> codes.  DNA uses the bit identity code = ((ch>>1) ^ (ch>>2)) & 3
@@ -1807,6 +1961,7 @@ static void fill_inst(const ac_dict *d, const void *text, uint64_t n, uint32_t f
     I->out_ids = d->d_out_ids;
     I->out_size = d->d_out_size;
     I->delta_sz = d->d_delta_sz;
+    I->n_ids = (uint32_t)d->host.out_ids.size();
     I->text = (const uint8_t *)text;
     I->out = out;
     I->count = (unsigned long long *)count;
@@ -1843,24 +1998,25 @@ static int allow_lds(K kernel, uint32_t bytes) {
 // once.  A block that could start only after others finish would run its
 // share of the work as a second, partial round.
 template <typename K>
-static uint32_t resident_grid(K kernel, uint32_t threads, uint32_t want) {
+static uint32_t resident_grid(K kernel, uint32_t threads, uint32_t want, uint32_t dyn_lds = 0) {
     static std::mutex mu;
-    static std::map<const void *, int> per_cu;
+    static std::map<std::pair<const void *, uint32_t>, int> per_cu;
+    const std::pair<const void *, uint32_t> key((const void *)kernel, dyn_lds);
     int n = 0;
     {
         std::lock_guard<std::mutex> lk(mu);
-        auto it = per_cu.find((const void *)kernel);
+        auto it = per_cu.find(key);
         if (it != per_cu.end()) n = it->second;
     }
     if (n == 0) {
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)kernel, (int)threads,
-                                                         0) != hipSuccess ||
+                                                         dyn_lds) != hipSuccess ||
             n <= 0) {
             (void)hipGetLastError();
             n = 1;
         }
         std::lock_guard<std::mutex> lk(mu);
-        per_cu[(const void *)kernel] = n;
+        per_cu[key] = n;
     }
     uint32_t cus = 1;
     if (device_limits(&cus, nullptr) != AC_OK) cus = 1;
@@ -1956,7 +2112,24 @@ static int launch_single(const Geom &g, const Inst &I, const Workspace &w, hipSt
                            nullptr, w.list_seg, w.list_state, w.list_moff, nullptr, w.totals,
                            w.seg_state, g.chunk / kSeg);
     }
-    {
+    // output-set tables for the staged dense emit: offsets (n_out + 1),
+    // then ids, both in LDS
+    const uint32_t n_out = (I.table_bytes - I.fo_bytes) / (I.sigma * 4u);
+    const uint64_t off_bytes = 4ull * (n_out + 1), ids_bytes = 4ull * I.n_ids;
+    uint32_t lds = 0;
+    if (device_limits(nullptr, &lds) != AC_OK) lds = 0;
+    if (((off_bytes + 15) & ~15ull) + ids_bytes + 1024 <= lds) {  // (+ the kernel's static LDS)
+        KTimer tm(AC_K_EMIT_DENSE, st);
+        const uint32_t dyn = (uint32_t)(((off_bytes + 15) & ~15ull) + ids_bytes);
+        int rc2 = allow_lds(k_emit_dense_lds<FMT>, dyn);
+        if (rc2) return rc2;
+        hipLaunchKernelGGL((k_emit_dense_lds<FMT>),
+                           dim3(resident_grid(k_emit_dense_lds<FMT>, kDenseLdsThreads,
+                                              g.grid_dense, dyn)),
+                           dim3(kDenseLdsThreads), dyn, st, I, w.list_seg, w.list_state,
+                           w.list_moff, w.totals, (uint32_t)off_bytes, (uint32_t)ids_bytes,
+                           I.out);
+    } else {
         KTimer tm(AC_K_EMIT_DENSE, st);
         hipLaunchKernelGGL((k_emit_dense<FMT, false>),
                            dim3(resident_grid(k_emit_dense<FMT, false>, kDenseThreads,
