@@ -70,6 +70,7 @@ struct ac_dict {
     uint32_t *d_out_size = nullptr;  // |out(s)| per output state
     uint32_t *d_delta_sz = nullptr;  // sigma 4: row offset | |out(target)| << 24 (count walk)
     uint16_t *d_hot16 = nullptr;  // first hot16_rows rows as 16-bit ids (0xFFFF: see table)
+    uint16_t *d_hot16c = nullptr;  // the same, output targets also 0xFFFF (count-table walk)
     uint32_t hot16_rows = 0;
     // sigma 4 only, when it fits LDS: transitions over two symbols,
     // states x 16 entries; entry = next row offset (next * 64), bit 31 set

@@ -69,6 +69,7 @@ struct Inst {
     const uint32_t *delta_sz;  // sigma 4: count table (row offset | |out(target)| << 24)
     uint32_t n_ids;            // entries of out_ids
     const uint16_t *hot16;   // 16-bit rows for the hybrid placement
+    const uint16_t *hot16c;  // the same with every output target escaped (count-table walk)
     const uint8_t *text;
     ac_match *out;
     unsigned long long *count;
@@ -687,7 +688,11 @@ __global__ __launch_bounds__(kMaxCountThreads) void k_count(
                 else if (lds_all)
                     load_lds_table(gtab, lb);
                 else  // 16-bit rows, then zeros up to lb
-                    load_lds_table(make_rsrc(uniform(I.hot16), ((hot >> 1) + 3u) & ~3u), lb);
+                    load_lds_table(make_rsrc(MODE == kCountHybrid && FMT == AC_TEXT_2BIT
+                                                 ? uniform(I.hot16c)
+                                                 : uniform(I.hot16),
+                                             ((hot >> 1) + 3u) & ~3u),
+                                   lb);
                 __syncthreads();
             }
             cur = (int)inst;
@@ -1623,8 +1628,12 @@ int upload_dict(ac_dict *d) {
     // (+2 entries: the LDS copy reads whole 32-bit words)
     std::vector<uint16_t> hot16((size_t)std::max<uint32_t>(hot_rows, 1) * T.sigma + 2, 0);
     for (size_t i = 0; i < (size_t)hot_rows * T.sigma; ++i)
-        hot16[i] = T.delta[i] < 0xFFFFu && T.delta[i] < T.first_output ? (uint16_t)T.delta[i]
-                                                                        : (uint16_t)0xFFFFu;
+        hot16[i] = T.delta[i] < 0xFFFFu ? (uint16_t)T.delta[i] : (uint16_t)0xFFFFu;
+    // for the count-table walk, transitions into output states are read from
+    // the 32-bit count table (which carries the set sizes): escape them too
+    std::vector<uint16_t> hot16c(hot16);
+    for (size_t i = 0; i < (size_t)hot_rows * T.sigma; ++i)
+        if (T.delta[i] >= T.first_output) hot16c[i] = 0xFFFFu;
     d->hot16_rows = hot_rows;
     // two-symbol table, when it fits the count kernel's LDS
     std::vector<uint32_t> d2;
@@ -1671,6 +1680,7 @@ int upload_dict(ac_dict *d) {
         hipMalloc((void **)&d->d_out_ids, ids_bytes) != hipSuccess ||
         hipMalloc((void **)&d->d_out_size, sizes.size() * 4) != hipSuccess ||
         hipMalloc((void **)&d->d_hot16, hot16.size() * 2) != hipSuccess ||
+        hipMalloc((void **)&d->d_hot16c, hot16c.size() * 2) != hipSuccess ||
         (!dsz.empty() && hipMalloc((void **)&d->d_delta_sz, dsz.size() * 4) != hipSuccess) ||
         (!d2.empty() && hipMalloc((void **)&d->d_delta2, d2.size() * 4) != hipSuccess) ||
         (!go.empty() && (hipMalloc((void **)&d->d_go, go.size() * 4) != hipSuccess ||
@@ -1688,6 +1698,8 @@ int upload_dict(ac_dict *d) {
          hipMemcpy(d->d_out_ids, T.out_ids.data(), T.out_ids.size() * 4, hipMemcpyHostToDevice) !=
              hipSuccess) ||
         hipMemcpy(d->d_hot16, hot16.data(), hot16.size() * 2, hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(d->d_hot16c, hot16c.data(), hot16c.size() * 2, hipMemcpyHostToDevice) !=
             hipSuccess ||
         (!dsz.empty() &&
          hipMemcpy(d->d_delta_sz, dsz.data(), dsz.size() * 4, hipMemcpyHostToDevice) !=
@@ -1716,6 +1728,8 @@ void release_dict(ac_dict *d) {
     if (d->d_out_size) (void)hipFree(d->d_out_size);
     d->d_out_size = nullptr;
     if (d->d_hot16) (void)hipFree(d->d_hot16);
+    if (d->d_hot16c) (void)hipFree(d->d_hot16c);
+    d->d_hot16c = nullptr;
     if (d->d_delta_sz) (void)hipFree(d->d_delta_sz);
     d->d_delta_sz = nullptr;
     if (d->d_delta2) (void)hipFree(d->d_delta2);
@@ -1980,6 +1994,7 @@ static void fill_inst(const ac_dict *d, const void *text, uint64_t n, uint32_t f
     I->lds_all = pl.lds_all;
     I->lds_bytes = pl.lds_bytes;
     I->hot16 = d->d_hot16;
+    I->hot16c = d->d_hot16c;
     const RowDiv rd = make_row_div(d->host.sigma);
     I->div_tz = rd.tz;
     I->div_inv = rd.inv;
