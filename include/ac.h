@@ -262,11 +262,16 @@ int ac_scan_batch(const ac_batch_item *items, uint32_t n_items, const ac_tune *t
 
 /* ---------------------------------------------------------------- timing
  * Kernel timing for measurement.  While enabled, every call above records a
- * pair of hipEvents on its stream around each kernel it launches (do not
- * enable it while a stream is being captured into a graph).  ac_timing_read
+ * pair of hipEvents on its stream around each timed kernel it launches (do
+ * not enable it while a stream is being captured into a graph).  on: 0 off,
+ * AC_TIMING_ALL every kind, or AC_TIMING_KIND(k) bits for chosen kinds only
+ * (each event pair adds a little time to the stream, so a measurement of
+ * the whole sequence can time just the kernel it needs).  ac_timing_read
  * waits for the recorded events, adds their elapsed times to per-kind totals
  * and returns them: ms[k] and launches[k] for k < AC_K_KINDS (arrays of
  * AC_K_KINDS entries, either may be NULL); reset != 0 clears the totals. */
+#define AC_TIMING_ALL 1
+#define AC_TIMING_KIND(k) (2 << (k))
 #define AC_K_ENCODE 0   /* ac_encode                                   */
 #define AC_K_COUNT 1    /* pass 1: walk chunks, count matches per segment */
 #define AC_K_OFFSETS 2  /* prefix sums over tiles                         */

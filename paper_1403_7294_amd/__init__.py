@@ -57,6 +57,13 @@ AC_SORT_BY_END = 1
 (AC_K_ENCODE, AC_K_COUNT, AC_K_OFFSETS, AC_K_SCATTER, AC_K_EMIT, AC_K_TOTALS, AC_K_EMIT_DENSE,
  AC_K_PFAC, AC_K_SORT) = range(9)
 AC_K_KINDS = 9
+AC_TIMING_ALL = 1
+
+
+def AC_TIMING_KIND(k: int) -> int:
+    return 2 << k
+
+
 KERNEL_NAMES = ["encode", "count", "offsets", "scatter", "emit", "totals", "emit_dense", "pfac",
                 "sort"]
 
@@ -371,8 +378,15 @@ def ac_device_info() -> Tuple[int, int]:
     return cu.value, lds.value
 
 
-def ac_timing_enable(on: bool) -> None:
-    _check(lib().ac_timing_enable(1 if on else 0), "ac_timing_enable")
+def ac_timing_enable(on, kinds=None) -> None:
+    """on: True/False for every kernel kind; kinds: an iterable of AC_K_*
+    values to time only those."""
+    v = 1 if on else 0
+    if on and kinds is not None:
+        v = 0
+        for k in kinds:
+            v |= AC_TIMING_KIND(k)
+    _check(lib().ac_timing_enable(v), "ac_timing_enable")
 
 
 def ac_timing_read(reset: bool = False):

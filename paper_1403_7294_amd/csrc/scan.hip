@@ -1750,7 +1750,7 @@ struct TimedPair {
     hipEvent_t a, b;
 };
 static std::mutex g_tm_mu;
-static bool g_tm_on = false;
+static uint32_t g_tm_mask = 0;  // bit k: time kernels of kind k
 static std::vector<TimedPair> g_tm_pending;
 static std::vector<hipEvent_t> g_tm_free;
 static double g_tm_ms[AC_K_KINDS];
@@ -1777,7 +1777,7 @@ struct KTimer {
     hipEvent_t a = nullptr;
     KTimer(int k, hipStream_t s) : kind(k), st(s) {
         std::lock_guard<std::mutex> lk(g_tm_mu);
-        if (!g_tm_on) return;
+        if (!(g_tm_mask >> kind & 1u)) return;
         a = tm_event();
         if (a) (void)hipEventRecord(a, st);
     }
@@ -2168,8 +2168,10 @@ int ac_device_info(uint32_t *compute_units, uint32_t *lds_bytes_per_block) {
 }
 
 int ac_timing_enable(int on) {
+    const uint32_t all = (1u << AC_K_KINDS) - 1u;
+    if (on < 0 || (on != AC_TIMING_ALL && ((uint32_t)on >> 1) & ~all)) return AC_E_INVALID;
     std::lock_guard<std::mutex> lk(g_tm_mu);
-    g_tm_on = on != 0;
+    g_tm_mask = on == AC_TIMING_ALL ? all : (uint32_t)on >> 1;
     return AC_OK;
 }
 

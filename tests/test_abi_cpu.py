@@ -60,6 +60,14 @@ def test_build_rejects(pats, sigma, code):
     assert e.value.status == code
 
 
+def test_timing_mask_validation():
+    # a mask naming kinds past AC_K_KINDS, or a negative value, is rejected
+    assert ac.lib().ac_timing_enable(ac.AC_TIMING_KIND(ac.AC_K_KINDS)) == ac.AC_E_INVALID
+    assert ac.lib().ac_timing_enable(-2) == ac.AC_E_INVALID
+    assert ac.lib().ac_timing_enable(ac.AC_TIMING_KIND(ac.AC_K_COUNT)) == ac.AC_OK
+    assert ac.lib().ac_timing_enable(0) == ac.AC_OK
+
+
 def test_scan_needs_device_tables():
     d = ac.ac_build([[0, 1]], sigma=4, host_only=True)
     assert d.info.has_device == 0

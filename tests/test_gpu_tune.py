@@ -73,3 +73,22 @@ def test_autotune_batch_exact():
     for k, w in enumerate(wants):
         assert c[k] == len(w)
         assert np.array_equal(ac.match_keys(outs[k][:len(w)]), w), k
+
+
+def test_timing_of_chosen_kinds_only():
+    # with a kind mask, only those kernels are timed (the others record no
+    # events); the scan's result does not depend on timing
+    torch = torch_cuda()
+    inst = W.dna_small()
+    d = ac.ac_build(inst.patterns, sigma=4)
+    t = device_text(inst, ac.AC_TEXT_2BIT)
+    want = oracle.Machine(inst.patterns, 4).scan_keys(inst.text)
+    ac.ac_timing_enable(True, kinds=[ac.AC_K_COUNT, ac.AC_K_EMIT_DENSE])
+    ac.ac_timing_read(reset=True)
+    out, total = ac.scan(d, t, ac.AC_TEXT_2BIT, n=len(inst.text))
+    torch.cuda.synchronize()
+    tm = ac.ac_timing_read(reset=True)
+    ac.ac_timing_enable(False)
+    assert total == len(want) and np.array_equal(ac.match_keys(out), want)
+    assert tm["count"][1] >= 1 and tm["emit_dense"][1] >= 1
+    assert tm["scatter"][1] == 0 and tm["emit"][1] == 0 and tm["offsets"][1] == 0
