@@ -357,15 +357,20 @@ __device__ __forceinline__ void walk_count_h16(const HotTable16 &tab, const UTex
         s[c] = 0;
         r[c] = ChunkOut{0, 0, 0};
     }
-    for (uint32_t i = 0; i < warm; ++i) {
-        uint32_t x[CH];
-        bool live[CH];
+    // Text comes in batches: the warm-up words and each group of four
+    // segments (256 bases) are loaded together, so the walk waits for text
+    // once per group -- on gfx9 the wait for a table lookup also waits for
+    // every older load, so a load per segment would stall once per segment.
+    constexpr uint32_t G = 4;
+    u32x4 ct[CH][G];
+    auto load_group = [&](uint32_t g0) {
 #pragma unroll
-        for (int c = 0; c < CH; ++c) {
-            const int w = (int)w0[c] - (int)warm + (int)i;
-            x[c] = txt.word(w);
-            live[c] = w >= 0;
-        }
+        for (int c = 0; c < CH; ++c)
+#pragma unroll
+            for (uint32_t p = 0; p < G; ++p)
+                ct[c][p] = g0 + p < spc ? txt.vec_once(w0[c] + WPS * (g0 + p)) : u32x4{0, 0, 0, 0};
+    };
+    auto warm_word = [&](uint32_t x[CH], const bool live[CH]) {
 #pragma unroll
         for (uint32_t k = 0; k < SPW; ++k) {
             uint32_t a[CH], ns[CH];
@@ -375,16 +380,43 @@ __device__ __forceinline__ void walk_count_h16(const HotTable16 &tab, const UTex
 #pragma unroll
             for (int c = 0; c < CH; ++c) s[c] = live[c] ? ns[c] & kRowBits : s[c];
         }
+    };
+    if (warm <= 2) {
+        // (patterns of up to 33 bases) the warm-up words with the first group
+        uint32_t wx[CH][2];
+#pragma unroll
+        for (int c = 0; c < CH; ++c)
+#pragma unroll
+            for (uint32_t i = 0; i < 2; ++i)
+                wx[c][i] = i < warm ? txt.word((int)w0[c] - (int)warm + (int)i) : 0u;
+        load_group(0);
+        for (uint32_t i = 0; i < warm; ++i) {
+            uint32_t x[CH];
+            bool live[CH];
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                x[c] = i == 0 ? wx[c][0] : wx[c][1];
+                live[c] = (int)w0[c] - (int)warm + (int)i >= 0;
+            }
+            warm_word(x, live);
+        }
+    } else {
+        for (uint32_t i = 0; i < warm; ++i) {
+            uint32_t x[CH];
+            bool live[CH];
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const int w = (int)w0[c] - (int)warm + (int)i;
+                x[c] = txt.word(w);
+                live[c] = w >= 0;
+            }
+            warm_word(x, live);
+        }
+        load_group(0);
     }
-    // the next two segments' text (one 16-byte vector each) in flight
-    constexpr uint32_t PD = 2;
-    u32x4 nx[CH][PD];
-#pragma unroll
-    for (int c = 0; c < CH; ++c)
-#pragma unroll
-        for (uint32_t p = 0; p < PD; ++p)
-            nx[c][p] = p < spc ? txt.vec_once(w0[c] + WPS * p) : u32x4{0, 0, 0, 0};
     for (uint32_t g = 0; g < spc; ++g) {
+        const uint32_t gi = g % G;
+        if (gi == 0 && g > 0) load_group(g);
         uint32_t qs[CH][4], sm[CH], he[CH], hq[CH];
         u32x4 x4[CH];
 #pragma unroll
@@ -392,9 +424,7 @@ __device__ __forceinline__ void walk_count_h16(const HotTable16 &tab, const UTex
             sm[c] = 0;
             he[c] = 0;  // an output entry | its position in the word (0: none yet)
             hq[c] = 0;  // the word it was seen in
-            x4[c] = nx[c][0];
-            nx[c][0] = nx[c][1];
-            if (g + PD < spc) nx[c][1] = txt.vec_once(w0[c] + WPS * (g + PD));
+            x4[c] = gi == 0 ? ct[c][0] : gi == 1 ? ct[c][1] : gi == 2 ? ct[c][2] : ct[c][3];
         }
 #pragma unroll
         for (uint32_t q = 0; q < 4; ++q) {
