@@ -1513,12 +1513,27 @@ __global__ __launch_bounds__(256) void k_encode(const uint8_t *__restrict__ in, 
 // letters become one 32-bit store.  Four letters are handled per 32-bit
 // word at once: code = ((ch>>1) ^ (ch>>2)) & 3 in every byte, then the four
 // 2-bit fields are gathered into one byte.  A byte is valid when (ch | 0x20)
-// is one of a c g t; the exact per-byte zero test
-// z(v) = ~(((v & 0x7F..) + 0x7F..) | v) & 0x80.. has no carries between
-// bytes.  The last partial wave (and unaligned buffers) take byte loads and
-// stores, with letters past n neither counted nor stored.
+// is one of a c g t, which is the case exactly when it equals the lowercase
+// letter of its own code ('A' 'C' 'G' 'T' and their lowercase forms map to
+// codes 0 1 2 3, and (ch | 0x20) = letter leaves only those two forms).  One
+// byte permute looks the four letters up at once, and the exact per-byte
+// zero test z(v) = ~(((v & 0x7F..) + 0x7F..) | v) & 0x80.., which has no
+// carries between bytes, compares them.  The kernel is bound by its integer
+// work, so one lookup and one test per word in place of four tests matter.
+// The last partial wave (and unaligned buffers) take byte loads and stores,
+// with letters past n neither counted nor stored.
 __device__ __forceinline__ uint32_t zero_bytes(uint32_t v) {
     return ~(((v & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | v) & 0x80808080u;
+}
+
+// Codes of the four letters of x (bits 0-1 of each byte, invalid letters
+// included) and the valid-letter mask (0x80 in each valid byte).
+__device__ __forceinline__ uint32_t dna_codes4(uint32_t x, uint32_t &ok) {
+    constexpr uint32_t kLetters = 0x74676361u;  // bytes 0..3: 'a' 'c' 'g' 't'
+    const uint32_t t = ((x >> 1) ^ (x >> 2)) & 0x03030303u;
+    // selectors 0..3 pick bytes of the table (both operands hold it)
+    ok = zero_bytes((x | 0x20202020u) ^ __builtin_amdgcn_perm(kLetters, kLetters, t));
+    return t;
 }
 
 __global__ __launch_bounds__(256) void k_encode_dna2(const uint8_t *__restrict__ in, uint64_t n,
@@ -1541,12 +1556,9 @@ __global__ __launch_bounds__(256) void k_encode_dna2(const uint8_t *__restrict__
             uint32_t packed = 0;
 #pragma unroll
             for (int w = 0; w < 4; ++w) {
-                const uint32_t x = v[q][w];
-                const uint32_t l = x | 0x20202020u;
-                const uint32_t ok = zero_bytes(l ^ 0x61616161u) | zero_bytes(l ^ 0x63636363u) |
-                                    zero_bytes(l ^ 0x67676767u) | zero_bytes(l ^ 0x74747474u);
+                uint32_t ok;
+                const uint32_t t = dna_codes4(v[q][w], ok) & (ok >> 7) * 3u;
                 bad += __builtin_popcount(~ok & 0x80808080u);
-                const uint32_t t = ((x >> 1) ^ (x >> 2)) & (ok >> 7) * 3u;
                 packed |= ((t | (t >> 6) | (t >> 12) | (t >> 18)) & 0xFFu) << (8 * w);
             }
             *(uint32_t *)(out + (wb + 1024u * q + 16u * lane) / 4) = packed;
@@ -1573,17 +1585,15 @@ __global__ __launch_bounds__(256) void k_encode_dna2(const uint8_t *__restrict__
                 uint32_t packed = 0;
 #pragma unroll
                 for (int w = 0; w < 4; ++w) {
-                    const uint32_t x = v[q][w];
-                    const uint32_t l = x | 0x20202020u;
-                    const uint32_t ok = zero_bytes(l ^ 0x61616161u) | zero_bytes(l ^ 0x63636363u) |
-                                        zero_bytes(l ^ 0x67676767u) | zero_bytes(l ^ 0x74747474u);
+                    uint32_t ok;
+                    const uint32_t c = dna_codes4(v[q][w], ok);
                     const int64_t rem = (int64_t)n - (int64_t)(p + 16u * q + 4u * w);
                     const uint32_t live = rem >= 4 ? 0x80808080u
                                           : rem <= 0 ? 0u
                                                      : (uint32_t)((1ull << (8 * rem)) - 1u) &
                                                            0x80808080u;
                     bad += __builtin_popcount(~ok & live);
-                    const uint32_t t = ((x >> 1) ^ (x >> 2)) & ((ok & live) >> 7) * 3u;
+                    const uint32_t t = c & ((ok & live) >> 7) * 3u;
                     packed |= ((t | (t >> 6) | (t >> 12) | (t >> 18)) & 0xFFu) << (8 * w);
                 }
                 o[q] = packed;
