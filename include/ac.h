@@ -187,6 +187,24 @@ int ac_scan(const ac_dict *dict, const void *d_text, uint64_t n, uint32_t fmt,
             const ac_tune *tune, void *d_workspace, uint64_t workspace_bytes,
             void *stream);
 
+/* ac_scan_noalloc: ac_scan for callers that cannot allocate memory (code
+ * under hipGraph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Arguments, results and errors as for ac_scan, without a
+ * workspace argument: the workspace is a device array of
+ * AC_NOALLOC_MAX_WORKSPACE bytes inside the library, one per device, held
+ * from the library's load until the process ends.  The call allocates no
+ * memory (no hipMalloc, no stream-ordered allocation) and enqueues kernels
+ * only.  AC_E_TOO_LARGE when ac_scan_workspace_size(dict, n, fmt, tune)
+ * exceeds AC_NOALLOC_MAX_WORKSPACE (about 60 M symbols at the default launch
+ * shape); AC_E_INVALID for a partitioned dictionary (its scan allocates).
+ * Every call on one device shares that device's array, which keeps the last
+ * call's contents: calls that overlap on one device (several streams or
+ * host threads) race and must be serialised by the caller. */
+#define AC_NOALLOC_MAX_WORKSPACE (64ull << 20)
+int ac_scan_noalloc(const ac_dict *dict, const void *d_text, uint64_t n, uint32_t fmt,
+                    ac_match *d_out, uint64_t capacity, uint64_t *d_count, const ac_tune *tune,
+                    void *stream);
+
 /* ---------------------------------------------------------------- variants
  * ac_build_partitioned: the paper's second design (section IV.A, Figure 3):
  * the pattern list is split into `parts` contiguous slices of about equal

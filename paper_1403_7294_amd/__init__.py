@@ -51,9 +51,10 @@ ABI_SYMBOLS = [
     "ac_scan_workspace_size", "ac_scan", "ac_batch_create", "ac_batch_run",
     "ac_batch_destroy", "ac_scan_batch", "ac_status_str", "ac_device_info",
     "ac_timing_enable", "ac_timing_read", "ac_build_partitioned", "ac_dict_parts",
-    "ac_scan_pfac", "ac_sort_workspace_size", "ac_sort_matches",
+    "ac_scan_pfac", "ac_sort_workspace_size", "ac_sort_matches", "ac_scan_noalloc",
 ]
 AC_SORT_BY_END = 1
+AC_NOALLOC_MAX_WORKSPACE = 64 << 20
 (AC_K_ENCODE, AC_K_COUNT, AC_K_OFFSETS, AC_K_SCATTER, AC_K_EMIT, AC_K_TOTALS, AC_K_EMIT_DENSE,
  AC_K_PFAC, AC_K_SORT) = range(9)
 AC_K_KINDS = 9
@@ -146,6 +147,8 @@ def lib():
     L.ac_scan_workspace_size.restype = i
     L.ac_scan.argtypes = [P, P, u64, u32, P, u64, P, ctypes.POINTER(ac_tune), P, u64, P]
     L.ac_scan.restype = i
+    L.ac_scan_noalloc.argtypes = [P, P, u64, u32, P, u64, P, ctypes.POINTER(ac_tune), P]
+    L.ac_scan_noalloc.restype = i
     L.ac_batch_create.argtypes = [ctypes.POINTER(ac_batch_item), u32, ctypes.POINTER(ac_tune),
                                   ctypes.POINTER(P)]
     L.ac_batch_create.restype = i
@@ -334,6 +337,16 @@ def ac_scan(d: "Dict", text_dev, n: int, fmt: int, out_dev, capacity: int, count
                          out_dev.data_ptr() if capacity else None, capacity,
                          count_dev.data_ptr(), _tune_ref(tune), ws, wsb,
                          _stream_ptr(stream)), "ac_scan")
+
+
+def ac_scan_noalloc(d: "Dict", text_dev, n: int, fmt: int, out_dev, capacity: int, count_dev,
+                    tune=None, stream=None) -> None:
+    """ac_scan with the library's own device scratch array as workspace: no
+    memory is allocated (see AC_NOALLOC_MAX_WORKSPACE)."""
+    _check(lib().ac_scan_noalloc(d.handle, text_dev.data_ptr() if n else None, n, fmt,
+                                 out_dev.data_ptr() if capacity else None, capacity,
+                                 count_dev.data_ptr(), _tune_ref(tune), _stream_ptr(stream)),
+           "ac_scan_noalloc")
 
 
 def _items(items) -> Tuple[ctypes.Array, list]:

@@ -2197,6 +2197,33 @@ static int launch_single(const Geom &g, const Inst &I, const Workspace &w, hipSt
     return AC_OK;
 }
 
+// Workspace of ac_scan_noalloc: the scratch memory of one scan, kept in a
+// file-scope device array so that a scan can run where allocating is not
+// allowed.  Each device that loads the library holds its own copy until the
+// process ends.  In host code the array's name is a host-side stand-in, not a
+// device address: the device address is taken once per device with
+// hipGetSymbolAddress (with that device current) and only that address is
+// passed to kernels.
+constexpr uint64_t kScratchBytes = AC_NOALLOC_MAX_WORKSPACE;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static std::mutex g_scratch_mu;
+static void *g_scratch[64];
+
+static int scratch_address(void **p) {
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return AC_E_HIP;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *q = nullptr;
+        HIP_OK(hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)));
+        if (!q) return AC_E_HIP;
+        g_scratch[dev] = q;
+    }
+    *p = g_scratch[dev];
+    return AC_OK;
+}
+
 }  // namespace acx
 
 using namespace acx;
@@ -2310,6 +2337,28 @@ int ac_scan(const ac_dict *d, const void *d_text, uint64_t n, uint32_t fmt, ac_m
                              : launch_single<AC_TEXT_U8>(g, I, w, st);
     if (own) (void)hipFreeAsync(ws, st);
     return rc;
+}
+
+int ac_scan_noalloc(const ac_dict *d, const void *d_text, uint64_t n, uint32_t fmt,
+                    ac_match *d_out, uint64_t capacity, uint64_t *d_count, const ac_tune *tune,
+                    void *stream) {
+    if (!d || !d_count) return AC_E_INVALID;
+    if (capacity && !d_out) return AC_E_INVALID;
+    if (!d->parts.empty()) return AC_E_INVALID;  // the partitioned scan allocates
+    if (!d->d_delta) return AC_E_NO_DEVICE;
+    int rc = validate_text(d, d_text, n, fmt);
+    if (rc) return rc;
+    uint64_t need = 0;
+    if (n) {
+        rc = ac_scan_workspace_size(d, n, fmt, tune, &need);
+        if (rc) return rc;
+    }
+    if (need > kScratchBytes) return AC_E_TOO_LARGE;
+    void *ws = nullptr;
+    rc = scratch_address(&ws);
+    if (rc) return rc;
+    // with a workspace given, ac_scan enqueues kernels only
+    return ac_scan(d, d_text, n, fmt, d_out, capacity, d_count, tune, ws, kScratchBytes, stream);
 }
 
 int ac_encode(const uint8_t *d_ascii, uint64_t n, uint32_t alphabet, uint32_t fmt, void *d_out,
