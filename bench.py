@@ -60,6 +60,35 @@ def measured_traffic(kernel, workload):
     return e.get("bytes_per_launch")
 
 
+# nominal LDS lookup peak: 32 banks x 4 B per clock per CU, conflict-free
+LDS_LOOKUP_PEAK = 32 * CUS * CLOCK_GHZ * 1e9
+
+
+def scan_roofline(n, matches, ms, text_bytes_per_base, kernel_sum_us, traffic=None):
+    """The scan's place under its roofs (the survey's measurement rule):
+    bases/s divided by min(HBM peak / HBM bytes per base, LDS lookup peak /
+    one lookup per base).  HBM bytes per base are the algorithmic ones: the
+    text read once plus 8 bytes per match written."""
+    bpb = text_bytes_per_base + 8.0 * matches / n
+    bases_s = n / (ms * 1e-3)
+    hbm_roof = HBM_PEAK_GBS * 1e9 / bpb
+    lds_roof = LDS_LOOKUP_PEAK
+    bound = "hbm" if hbm_roof <= lds_roof else "lds"
+    achieved = bases_s * bpb / 1e9
+    out = {"bound": bound, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(bases_s / min(hbm_roof, lds_roof), 4), "traffic": traffic,
+           "scope": "the scan: every kernel from the packed text in HBM to all matches "
+                    "written, one launch sequence", "scan_us": round(ms * 1e3, 2),
+           "kernel_sum_us": round(kernel_sum_us, 2),
+           "bytes_per_base": round(bpb, 4), "bases_per_s": round(bases_s, 1),
+           "hbm_roof_bases_per_s": round(hbm_roof, 1), "lds_roof_bases_per_s": lds_roof,
+           "frac_hbm": round(bases_s / hbm_roof, 4), "frac_lds": round(bases_s / lds_roof, 4)}
+    if bound == "lds":
+        out.update(achieved=round(bases_s / 1e9, 2), peak=round(lds_roof / 1e9, 1),
+                   unit="G lookups/s")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,6 +99,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the partitioned / failure-less / two-symbol comparisons")
+    ap.add_argument("--no-peaks", action="store_true",
+                    help="skip the microbenchmarks of the HBM, LDS and gather ceilings")
     ap.add_argument("--serve-requests", type=int, default=10_000,
                     help="requests timed at the fixed arrival rate")
     ap.add_argument("--scale", type=float, default=1.0, help="shrink the workload (testing)")
@@ -211,25 +242,24 @@ def main():
     lds_lookup_peak = 32 * CUS * CLOCK_GHZ * 1e9
     rooflines["count"]["lds_lookup_peak_per_s"] = lds_lookup_peak
     rooflines["count"]["lookup_frac"] = rooflines["count"]["lookups_per_s"] / lds_lookup_peak
-    # the dominant kernel's roofline uses its duration from the timed steps
+    # the dominant kernel's figures, from its duration in the timed steps
     dom = dom_name
     live_ms = live[0] / max(1, live[1])
     r = dict(rooflines[dom])
-    r["achieved"] = r["algorithmic_bytes"] / (live_ms * 1e-3) / 1e9
-    r["avg_us"] = live_ms * 1e3
+    dominant = {"kernel": dom, "avg_us": round(live_ms * 1e3, 2),
+                "achieved": round(r["algorithmic_bytes"] / (live_ms * 1e-3) / 1e9, 1),
+                "peak": r["peak"], "unit": r["unit"],
+                "frac": round(r["algorithmic_bytes"] / (live_ms * 1e-3) / 1e9 / r["peak"], 4),
+                "traffic": measured_traffic(dom, "dna_dense")}
     if dom == "count":
-        r["lookups_per_s"] = n / (live_ms * 1e-3)
-        r["lookup_frac"] = r["lookups_per_s"] / lds_lookup_peak
-    roofline = {"bound": r["bound"], "achieved": round(r["achieved"], 1), "peak": r["peak"],
-                "unit": r["unit"], "frac": round(r["achieved"] / r["peak"], 4),
-                "traffic": measured_traffic(dom, "dna_dense"), "kernel": dom,
-                "kernel_avg_us": round(r["avg_us"], 2)}
-    if dom == "count":
-        # the count pass moves little HBM data; what bounds it is one
-        # dependent table lookup per base (LDS, or L2 for rows not in LDS)
-        roofline["lookups"] = {"achieved_per_s": round(r["lookups_per_s"], 1),
-                               "lds_peak_per_s": lds_lookup_peak,
-                               "frac": round(r["lookup_frac"], 4)}
+        dominant["lookups_per_s"] = round(n / (live_ms * 1e-3), 1)
+        dominant["lookup_frac"] = round(n / (live_ms * 1e-3) / lds_lookup_peak, 4)
+    # the scan's roofline: bases/s against the lower of the HBM roof at the
+    # scan's algorithmic bytes per base (packed text read + 8 B per match)
+    # and the LDS roof at one table lookup per base
+    roofline = scan_roofline(n, total, scan_ms, text_bytes_per_base=0.25,
+                             kernel_sum_us=sum(avg[k] for k in avg) * 1e3 - avg.get("encode", 0) * 1e3,
+                             traffic=measured_traffic("scan", "dna_dense"))
 
     cus, lds = ac.ac_device_info()
     lds_limit = lds - 512
@@ -258,6 +288,7 @@ def main():
                    "table_mib": round(info.table_bytes / 2**20, 3), "matches": total,
                    "text_format": "2-bit", "placement": placement},
         "roofline": roofline,
+        "dominant_kernel": dominant,
         "step_hbm_roofline": {"algorithmic_bytes": step_bytes,
                               "achieved_gbs": round(step_bytes / (step_ms * 1e-3) / 1e9, 1),
                               "frac": round(step_bytes / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
@@ -273,21 +304,32 @@ def main():
     # --------------------------------------------------------- CPU oracle
     if not args.no_cpu:
         import oracle
-        t = time.time()
         m = oracle.Machine(inst.patterns, 4)
-        pid, end = m.scan(inst.text)
-        cpu_s = time.time() - t
+        times = []
+        with pinned_to_one_core() as core:
+            for _ in range(3):
+                t = time.perf_counter()
+                pid, end = m.scan(inst.text)
+                times.append(time.perf_counter() - t)
+                if len(times) < 3:
+                    del pid, end
+        cpu_s = float(np.median(times))
         want = oracle.keys(pid, end)
         got = ac.match_keys(out)
         exact = bool(len(want) == total and np.array_equal(got, want))
-        log(f"[bench] oracle: {cpu_s:.2f} s for {n} bases; bit-exact: {exact}")
+        log(f"[bench] oracle: {cpu_s:.2f} s for {n} bases (median of 3, core {core}); "
+            f"bit-exact: {exact}")
         result["bit_exact"] = exact
         result["cpu_baseline"] = {"value": round(n / cpu_s / 1e9, 4), "unit": "Gbases/s",
                                   "cores": 1, "kind": "oracle",
-                                  "sample": f"the whole dna_dense text ({n} bases), build "
-                                            f"excluded, one thread",
+                                  "sample": f"the whole dna_dense text ({n} bases), scan only "
+                                            f"(build excluded), median of 3 runs, one thread "
+                                            f"pinned to host core {core}",
+                                  "host_cpu": host_cpu(),
                                   "speedup_gpu_step": round(result["value"] / (n / cpu_s / 1e9), 1)}
         del pid, end, want, got
+        # the paper's own parallel design on the host's cores (context only)
+        result["paper_design_cpu"] = bench_split_cpu(oracle, inst, result)
 
     # --------------------------------------------------------- batched vs plain
     if not args.no_batch:
@@ -298,6 +340,12 @@ def main():
         result["variants"] = bench_variants(args, torch, ac, W, inst, d, packed, out, total,
                                             scan_ms)
 
+    # --------------------------------------------------------- other configs
+    result["protein"] = bench_protein(args, torch, ac, W, dev, stream)
+    result["dna_small_graph"] = bench_small_graph(args, torch, ac, W, dev, stream)
+    if not args.no_peaks:
+        result["measured_peaks"] = bench_peaks(torch, result)
+
     # --------------------------------------------------------- build vs scan
     result["build_vs_scan"] = bench_build(args, ac, W, inst, step_ms)
 
@@ -307,6 +355,202 @@ def main():
 
     del out
     print(json.dumps(result), flush=True)
+
+
+class pinned_to_one_core:
+    """Run the enclosed CPU work on one host core (the first one this process
+    may use), then restore the process's affinity."""
+
+    def __enter__(self):
+        self.saved = os.sched_getaffinity(0)
+        self.core = min(self.saved)
+        os.sched_setaffinity(0, {self.core})
+        return self.core
+
+    def __exit__(self, *exc):
+        os.sched_setaffinity(0, self.saved)
+        return False
+
+
+def host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "os_cpu_count": os.cpu_count(),
+            "usable_cores": len(os.sched_getaffinity(0))}
+
+
+def bench_split_cpu(oracle, inst, result):
+    """The paper's second parallel design (pattern slices, one machine and one
+    POSIX thread each, every thread reading the whole text) on N = 1 and
+    N = all usable host cores, over a 12 MiB-base prefix of the dna_dense
+    text (the paper's Fig. 5 input size) with the full dictionary.  Timed as
+    the paper timed it (build + scan) and scan only; the N-thread speed-up
+    is quoted beside the paper's 9x (context, not a target)."""
+    text = inst.text[:12 << 20]
+    cores = len(os.sched_getaffinity(0))
+    rows = []
+    for parts in sorted({1, cores}):
+        r = oracle.split_run(inst.patterns, 4, text, parts)
+        rows.append({"threads": parts, "matches": int(r["counts"].sum()),
+                     "build_scan_s": round(r["wall_build_scan_s"], 4),
+                     "scan_only_s": round(r["wall_scan_s"], 4),
+                     "build_s_max_thread": round(float(r["build_s"].max()), 4),
+                     "gbases_s_build_scan": round(len(text) / r["wall_build_scan_s"] / 1e9, 4),
+                     "gbases_s_scan_only": round(len(text) / r["wall_scan_s"] / 1e9, 4)})
+    one, alln = rows[0], rows[-1]
+    res = {"design": "pattern list cut into N slices, one goto/failure machine and one "
+                     "POSIX thread per slice, every thread scans the whole text",
+           "sample": f"{len(text)} bases (prefix of dna_dense), 10,000 patterns",
+           "cores": cores, "host_cpu": host_cpu(), "runs": rows,
+           "speedup_n_over_1_build_scan": round(one["build_scan_s"] / alln["build_scan_s"], 2),
+           "speedup_n_over_1_scan_only": round(one["scan_only_s"] / alln["scan_only_s"], 2),
+           "paper_speedup_context": "9x: 16 threads of an 8-core Xeon X7560 over one thread "
+                                    "(abstract; section V words it as over a Pentium 4), "
+                                    "build + scan, the paper's own data",
+           "gpu_step_over_n_thread_scan_only": round(result["value"] / alln["gbases_s_scan_only"], 1)}
+    log(f"[bench] paper design on CPU: {cores} threads, build+scan speed-up "
+        f"{res['speedup_n_over_1_build_scan']}x, scan-only {res['speedup_n_over_1_scan_only']}x")
+    return res
+
+
+def bench_protein(args, torch, ac, W, dev, stream):
+    """The protein workload: 67,108,864 residues (20 letters, skewed
+    background) as letters in HBM, 5,000 patterns of 5-12 cut from the text.
+    A step encodes the letters to byte codes and scans; the scan is also
+    timed alone, and its output compared with the oracle's."""
+    inst = W.protein(scale=args.scale)
+    n = len(inst.text)
+    d = ac.ac_build(inst.patterns, sigma=20)
+    fmt = ac.AC_TEXT_U8
+    letters = torch.from_numpy(W.to_ascii(inst.text, W.PROTEIN)).to(dev)
+    codes = torch.empty(n, dtype=torch.uint8, device=dev)
+    ws = torch.empty(ac.ac_scan_workspace_size(d, n, fmt), dtype=torch.uint8, device=dev)
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    ac.ac_encode(letters, ac.AC_ALPHA_PROTEIN, fmt, codes)
+    dummy = torch.empty((1, 2), dtype=torch.int32, device=dev)
+    ac.ac_scan(d, codes, n, fmt, dummy, 0, count, workspace_dev=ws)
+    torch.cuda.synchronize()
+    total = int(count.item())
+    out = torch.empty((max(1, total), 2), dtype=torch.int32, device=dev)
+
+    def scan():
+        ac.ac_scan(d, codes, n, fmt, out, total, count, workspace_dev=ws)
+
+    def step():
+        ac.ac_encode(letters, ac.AC_ALPHA_PROTEIN, fmt, codes)
+        scan()
+
+    def timeit(fn, reps):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    step_ms = timeit(step, args.steps)
+    scan_ms = timeit(scan, args.steps)
+    ac.ac_timing_enable(True)
+    ac.ac_timing_read(reset=True)
+    for _ in range(args.steps):
+        scan()
+    torch.cuda.synchronize()
+    kt = ac.ac_timing_read(reset=True)
+    ac.ac_timing_enable(False)
+    kus = {k: round(v[0] / v[1] * 1e3, 2) for k, v in kt.items() if v[1]}
+    import oracle
+    want = oracle.Machine(inst.patterns, 20).scan_keys(inst.text)
+    exact = bool(total == len(want) and np.array_equal(ac.match_keys(out), want))
+    roof = scan_roofline(n, total, scan_ms, text_bytes_per_base=1.0,
+                         kernel_sum_us=sum(kus.values()),
+                         traffic=measured_traffic("scan", "protein"))
+    log(f"[bench] protein: step {step_ms:.3f} ms, scan {scan_ms:.3f} ms "
+        f"({n / scan_ms / 1e6:.1f} Gres/s), {total} matches, bit-exact {exact}; kernels {kus}")
+    info = d.info
+    return {"workload": "protein: 67,108,864 residues as letters in HBM (20 letters, skewed "
+                        "background, max 10 %, min 1.3 %), 5,000 patterns of 5-12 cut from "
+                        "the text; byte codes",
+            "residues": n, "patterns": inst.patterns.count, "states": info.states,
+            "table_mib": round(info.table_bytes / 2**20, 3), "matches": total,
+            "step_ms": round(step_ms, 4), "gbases_s_step": round(n / (step_ms * 1e-3) / 1e9, 3),
+            "scan_ms": round(scan_ms, 4), "gbases_s_scan": round(n / (scan_ms * 1e-3) / 1e9, 3),
+            "kernel_us": kus, "roofline": roof, "bit_exact": exact}
+
+
+def bench_small_graph(args, torch, ac, W, dev, stream):
+    """dna_small (1,048,576 bases as byte codes, 100 patterns): one scan takes
+    a few microseconds of GPU work, so it is timed as 100 scans captured in
+    one hipGraph and replayed, and also as single calls."""
+    inst = W.dna_small()
+    n = len(inst.text)
+    d = ac.ac_build(inst.patterns, sigma=4)
+    fmt = ac.AC_TEXT_U8
+    codes = torch.from_numpy(inst.text.copy()).to(dev)
+    ws = torch.empty(ac.ac_scan_workspace_size(d, n, fmt), dtype=torch.uint8, device=dev)
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    out, total = ac.scan(d, codes, fmt, n=n)
+    out = torch.full((total + 8, 2), -1, dtype=torch.int32, device=dev)
+    iters = 100
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        ac.ac_scan(d, codes, n, fmt, out, total, count, workspace_dev=ws, stream=s)
+        s.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            for _ in range(iters):
+                ac.ac_scan(d, codes, n, fmt, out, total, count, workspace_dev=ws, stream=s)
+    for _ in range(3):
+        g.replay()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    a.record(stream)
+    for _ in range(reps):
+        g.replay()
+    b.record(stream)
+    torch.cuda.synchronize()
+    per_scan_ms = a.elapsed_time(b) / (reps * iters)
+    import oracle
+    want = oracle.Machine(inst.patterns, 4).scan_keys(inst.text)
+    exact = bool(int(count.item()) == len(want) and
+                 np.array_equal(ac.match_keys(out[:len(want)]), want))
+    call_ms = _timed(torch, lambda: ac.ac_scan(d, codes, n, fmt, out, total, count,
+                                               workspace_dev=ws), 50)
+    log(f"[bench] dna_small: {per_scan_ms * 1e3:.2f} us per scan in a graph of {iters} "
+        f"({n / per_scan_ms / 1e6:.1f} Gbases/s); {call_ms * 1e3:.1f} us per call")
+    return {"workload": "dna_small: 1,048,576 uniform DNA bases as byte codes, 100 patterns of "
+                        "8-16 (50 cut, 50 random)", "matches": total,
+            "graph_iterations": iters, "us_per_scan_graph": round(per_scan_ms * 1e3, 3),
+            "gbases_s_graph": round(n / (per_scan_ms * 1e-3) / 1e9, 3),
+            "us_per_call_wall": round(call_ms * 1e3, 2),
+            "gbases_s_call_wall": round(n / (call_ms * 1e-3) / 1e9, 3), "bit_exact": exact}
+
+
+def bench_peaks(torch, result):
+    """Measured ceilings (the roofline denominators) beside the published
+    ones, and the scan's fractions of the measured ones."""
+    from paper_1403_7294_amd import microbench
+    m = microbench.measure(torch)
+    m["nominal"] = {"hbm_gbs": HBM_PEAK_GBS, "lds_lookups_per_s": LDS_LOOKUP_PEAK}
+    r = result["roofline"]
+    best_hbm = max(m["hbm_copy_gbs"], m["hbm_write_gbs"], m["hbm_read_gbs"])
+    m["scan_frac_of_measured_hbm"] = round(r["bases_per_s"] * r["bytes_per_base"] / 1e9 /
+                                           best_hbm, 4)
+    m["scan_frac_of_measured_write"] = round(r["bases_per_s"] * r["bytes_per_base"] / 1e9 /
+                                             m["hbm_write_gbs"], 4)
+    log(f"[bench] measured peaks: {m}")
+    return m
 
 
 def bench_batch(args, torch, ac, W, dev, stream):

@@ -16,6 +16,12 @@ Contents:
 * ``encode`` / ``pack2`` / ``unpack2`` -- the text encoding the scan reads:
                       letters -> codes, and DNA codes packed four per byte,
                       least significant bits first.
+* ``split_run``    -- the paper's own parallel design on host threads
+                      (section IV.A, second design, Fig. 3): N pattern
+                      slices, one machine and one POSIX thread each, every
+                      thread reading the whole text; plain C in
+                      ``ac_split.c`` over the same machine.  The CPU context
+                      baseline, timed build + scan and scan only.
 * ``chunk_scan``   -- the text-chunking rule (each chunk re-read from
                       ``max(0, start - (m_max - 1))``, reporting only ends
                       inside the chunk) applied to the oracle's scan.
@@ -34,7 +40,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["ac_oracle.c", "naive.c"]
+_SOURCES = ["ac_oracle.c", "naive.c", "ac_split.c"]
 _lib = None
 
 OK, E_INVALID, E_EMPTY, E_SYMBOL, E_TOO_LARGE, E_NOMEM = 0, -1, -2, -3, -4, -5
@@ -49,7 +55,7 @@ def build(force: bool = True) -> str:
             return _LIB_PATH
     tmp = _LIB_PATH + ".tmp%d" % os.getpid()
     subprocess.run(["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC",
-                    "-o", tmp] + srcs, check=True)
+                    "-pthread", "-o", tmp] + srcs, check=True)
     os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -91,6 +97,10 @@ def _open(path: str):
     lib.naive_scan.restype = i64
     lib.kmer_count.argtypes = [P, u64, P, P, u32, u32, P]
     lib.kmer_count.restype = ctypes.c_int
+    if hasattr(lib, "split_run"):  # absent from copies built without ac_split.c
+        d = ctypes.POINTER(ctypes.c_double)
+        lib.split_run.argtypes = [P, P, u32, u32, P, u64, u32, P, P, u64, P, d, d, P, P]
+        lib.split_run.restype = ctypes.c_int
     return lib
 
 
@@ -225,6 +235,48 @@ def kmer_count(text: np.ndarray, patterns, sigma: int) -> np.ndarray:
     if rc != 0:
         raise OracleError(rc)
     return c
+
+
+def split_run(patterns, sigma: int, text: np.ndarray, parts: int, collect: bool = False) -> dict:
+    """The paper's second parallel design with ``parts`` POSIX threads: slice
+    t of the pattern list (consecutive patterns, sizes within one) gets its
+    own machine and thread, and every thread scans the whole text.  Returns
+    the per-slice match counts, the wall time of one run that builds and
+    scans (what the paper timed) and of a second run of the same machines
+    that only scans, the per-thread build and scan times of the first run,
+    and, with ``collect``, the union of all slices' matches as sorted uint64
+    keys (global pattern ids)."""
+    lib = _load()
+    text = np.ascontiguousarray(text, dtype=np.uint8)
+    sym, off = _csr(patterns)
+    npat = len(off) - 1
+    counts = np.zeros(parts, dtype=np.uint64)
+    bs = np.zeros(parts, dtype=np.float64)
+    ss = np.zeros(parts, dtype=np.float64)
+    w1, w2 = ctypes.c_double(), ctypes.c_double()
+    cap = 0
+    pid = end = np.zeros(1, dtype=np.uint32)
+    while True:
+        rc = lib.split_run(_ptr(sym), _ptr(off), npat, sigma,
+                           _ptr(text) if len(text) else ctypes.c_void_p(0), len(text), parts,
+                           _ptr(pid) if cap else ctypes.c_void_p(0),
+                           _ptr(end) if cap else ctypes.c_void_p(0), cap, _ptr(counts),
+                           ctypes.byref(w1), ctypes.byref(w2), _ptr(bs), _ptr(ss))
+        if rc != OK:
+            raise OracleError(rc)
+        need = int(counts.max()) if parts else 0
+        if not collect or need <= cap:
+            break
+        cap = need
+        pid = np.empty(parts * cap, dtype=np.uint32)
+        end = np.empty(parts * cap, dtype=np.uint32)
+    res = {"parts": parts, "counts": counts, "wall_build_scan_s": w1.value,
+           "wall_scan_s": w2.value, "build_s": bs, "scan_s": ss}
+    if collect:
+        sel = np.concatenate([np.arange(t * cap, t * cap + int(counts[t])) for t in range(parts)]
+                             ) if cap else np.zeros(0, dtype=np.int64)
+        res["keys"] = np.sort(keys(pid[sel], end[sel]))
+    return res
 
 
 # ------------------------------------------------------------- text encoding

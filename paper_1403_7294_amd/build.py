@@ -3,7 +3,9 @@
     python -m paper_1403_7294_amd.build        (or build() from Python)
 
 Host sources are compiled by g++, the HIP source by hipcc for gfx950 only,
-and everything is linked into paper_1403_7294_amd/libac.so.
+and everything is linked into paper_1403_7294_amd/libac.so.  The roofline
+microbenchmarks (csrc/microbench.hip) become libac_microbench.so, which only
+the benchmark loads.
 """
 from __future__ import annotations
 
@@ -16,6 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libac.so")
+MB_LIB = os.path.join(HERE, "libac_microbench.so")  # roofline denominators (bench only)
 OBJ = os.path.join(HERE, "_build")
 
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
@@ -24,6 +27,7 @@ ARCH = "gfx950"
 
 HOST_SOURCES = ["automaton.cpp", "api.cpp"]
 HIP_SOURCES = ["scan.hip", "sort.hip"]
+MB_SOURCES = ["microbench.hip"]
 DEPS = ["internal.h", "batch.inc", "device_common.h"]
 
 # packed fp32 instructions are disabled on every HIP compile (they are never
@@ -61,6 +65,14 @@ def build(verbose: bool = False, extra_hip_flags=()) -> str:
     tmp = LIB + ".tmp%d" % os.getpid()
     _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs)
     os.replace(tmp, LIB)
+    mb_objs = []
+    for src in MB_SOURCES:
+        o = os.path.join(OBJ, src + ".o")
+        _run([HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", o])
+        mb_objs.append(o)
+    tmp = MB_LIB + ".tmp%d" % os.getpid()
+    _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + mb_objs)
+    os.replace(tmp, MB_LIB)
     return LIB
 
 

@@ -201,3 +201,26 @@ def test_partitioned_build_host():
     d3 = ac.ac_build_partitioned(pats, sigma=4, parts=3, host_only=True)
     assert len(ac.ac_dict_parts(d3)) == 3
     assert ac.ac_dict_parts(ac.ac_build(pats, sigma=4, host_only=True)) == []
+
+
+def test_microbench_library_exports_every_declared_symbol():
+    from paper_1403_7294_amd import microbench
+    src = open(os.path.join(ROOT, "include", "ac_microbench.h")).read()
+    declared = sorted(set(re.findall(r"^\s*int\s+(acb_\w+)\(", src, re.M)))
+    assert declared == sorted(microbench.SYMBOLS)
+    L = microbench.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def test_microbench_cycle_is_one_permutation_cycle():
+    from paper_1403_7294_amd.microbench import _cyclic_permutation
+    nxt = _cyclic_permutation(4096, 3)
+    assert np.array_equal(np.sort(nxt), np.arange(4096, dtype=np.uint32))
+    s, seen = 0, 0
+    while True:
+        s = int(nxt[s])
+        seen += 1
+        if s == 0:
+            break
+    assert seen == 4096
