@@ -724,14 +724,14 @@ def bench_serve(args, torch, ac, W):
     n_sat = 2000
     wl = W.serve(scale=args.scale, requests=n_sat + args.serve_requests)
     letters = [W.to_ascii(t, W.DNA) for t in wl.texts]
-    srv = Server(wl.dictionaries, budget_bytes=8 << 30, max_batch=64, streams=2)
+    srv = Server(wl.dictionaries, budget_bytes=8 << 30)
     log(f"[bench] serve: {len(letters)} requests, {sum(len(t) for t in letters)} bases, "
         f"8 dictionaries (setup {time.time() - t0:.1f} s)")
     # warm-up, then saturation: everything queued at once
     for f in [srv.submit(letters[k], int(wl.dict_of[k])) for k in range(64)]:
         f.result()
     srv.close()
-    srv = Server(wl.dictionaries, budget_bytes=8 << 30, max_batch=64, streams=2)
+    srv = Server(wl.dictionaries, budget_bytes=8 << 30)
     futs = [srv.submit(letters[k], int(wl.dict_of[k])) for k in range(n_sat)]
     sat_res = [f.result() for f in futs]
     sat = srv.close()
@@ -743,7 +743,7 @@ def bench_serve(args, torch, ac, W):
         out, total = ac.scan(srv.dicts[int(wl.dict_of[k])], dev, ac.AC_TEXT_U8)
         same &= bool(np.array_equal(ac.match_keys(out), sat_res[k]))
     rate = 0.7 * r_sat
-    srv = Server(wl.dictionaries, budget_bytes=8 << 30, max_batch=64, streams=2)
+    srv = Server(wl.dictionaries, budget_bytes=8 << 30)
     futs = run_poisson(srv, letters[n_sat:], wl.dict_of[n_sat:], wl.gaps[n_sat:], rate)
     for f in futs:
         f.result()

@@ -56,6 +56,7 @@ extern "C" {
 #define AC_E_OVERFLOW (-6)       /* workspace smaller than required          */
 #define AC_E_HIP (-7)            /* a HIP runtime call or launch failed      */
 #define AC_E_NO_DEVICE (-8)      /* dictionary was built without GPU tables  */
+#define AC_E_TIMEOUT (-9)        /* a wait ended before its request finished */
 
 #define AC_TEXT_U8 0
 #define AC_TEXT_2BIT 1
@@ -136,13 +137,16 @@ typedef struct {
 int ac_build(const uint8_t *symbols, const uint64_t *offsets, uint32_t n_patterns,
              const ac_build_opts *opts, ac_dict **out);
 
-/* Release a dictionary (host and device memory).  NULL is ignored.  The
- * caller must have synchronised every stream that uses it. */
+/* Release a dictionary built by stage 1 (section III.A): host and device
+ * memory.  NULL is ignored.  The caller must have synchronised every stream
+ * that uses it. */
 void ac_destroy(ac_dict *dict);
 
 int ac_dict_get_info(const ac_dict *dict, ac_dict_info *info);
 
-/* Host copies of the compiled tables, for inspection and CPU checks:
+/* Host copies of the compiled stage-1 tables (section III.A, Figures 1-2:
+ * the goto function completed through the failure function, and the output
+ * function), for inspection and CPU checks:
  *   delta    states*sigma entries: delta[s*sigma + a] = next state of s on
  *            symbol a (renumbered ids; root = 0).
  *   out_off  (states - first_output_state + 1) offsets into out_ids for the
@@ -154,7 +158,10 @@ int ac_debug_export(const ac_dict *dict, uint32_t *delta, uint32_t *out_off,
                     uint32_t *out_ids, uint32_t *depth);
 
 /* ---------------------------------------------------------------- encoding
- * ac_encode: d_ascii (n letters, device) -> d_out (device) as AC_TEXT_U8
+ * ac_encode: the input string of the matching stage (section III.A, read
+ * from a file of nucleotide or amino-acid letters in section IV.B) turned
+ * into symbol codes on the GPU.
+ * d_ascii (n letters, device) -> d_out (device) as AC_TEXT_U8
  * codes (n bytes) or, for AC_ALPHA_DNA only, AC_TEXT_2BIT ((n+3)/4 bytes,
  * unused bits of the last byte zero).  Letters outside the alphabet are
  * encoded as code 0 and counted into *d_invalid (device uint64, may be NULL;
@@ -237,7 +244,9 @@ int ac_dict_parts(const ac_dict *dict, uint32_t *parts, uint32_t *first_ids);
 int ac_scan_pfac(const ac_dict *dict, const void *d_text, uint64_t n, uint32_t fmt,
                  ac_match *d_out, uint64_t capacity, uint64_t *d_count, void *stream);
 
-/* ac_sort_matches: sort n device records in place into (end_pos,
+/* ac_sort_matches: put match records (section IV.B: each occurrence is a
+ * matched pattern and its position) into the canonical order of this
+ * library: sort n device records in place into (end_pos,
  * pattern_id) order -- the order ac_scan writes -- by a radix sort over the
  * low end_bits bits of end_pos (0 = 32) and all of pattern_id.  With
  * AC_SORT_BY_END only end_pos is sorted on, stably: enough when records with
@@ -250,8 +259,11 @@ int ac_sort_matches(ac_match *d_matches, uint64_t n, uint32_t flags, uint32_t en
                     void *d_workspace, uint64_t workspace_bytes, void *stream);
 
 /* ---------------------------------------------------------------- batches
- * One instance of a batch: its own dictionary, text, output and count,
- * with the meaning of the same-named ac_scan arguments. */
+ * Many independent matching jobs at once (section IV.A: the work is split
+ * into independent scans run in parallel; here each job is its own
+ * (dictionary, text) pair).  One instance of a batch: its own dictionary,
+ * text, output and count, with the meaning of the same-named ac_scan
+ * arguments. */
 typedef struct {
     const ac_dict *dict;
     const void *d_text;
@@ -263,20 +275,113 @@ typedef struct {
     uint64_t *d_count;
 } ac_batch_item;
 
-/* ac_batch_create: plan a batch once (work list of (instance, chunk range)
- * tiles grouped by instance, descriptors uploaded to the device, workspace
- * allocated) so that ac_batch_run only launches kernels: it can be replayed
- * and captured in a hipGraph.  The items' buffers must stay valid for the
- * life of the plan. */
+/* ac_batch_create (section IV.A, as above): plan a batch once (work list
+ * of (instance, chunk range) tiles grouped by instance, descriptors uploaded
+ * to the device, workspace allocated) so that ac_batch_run only launches
+ * kernels: it can be replayed and captured in a hipGraph.  The items'
+ * buffers must stay valid for the life of the plan; the plan owns its
+ * descriptor and workspace memory.  Errors as for ac_scan (checked for every
+ * item), AC_E_NOMEM. */
 int ac_batch_create(const ac_batch_item *items, uint32_t n_items, const ac_tune *tune,
                     ac_batch **out);
+/* ac_batch_run: enqueue the planned scans on `stream` (section IV.A, as
+ * above); results as for ac_scan, per item.  Runs of one plan must not
+ * overlap (they share its workspace).  AC_E_INVALID for a NULL plan. */
 int ac_batch_run(ac_batch *batch, void *stream);
+/* Release a plan; NULL is ignored.  Its runs must have completed. */
 void ac_batch_destroy(ac_batch *batch);
 
-/* ac_scan_batch: plan + run + release in one call (the plan's memory is
- * released after the stream reaches the end of the batch). */
+/* ac_scan_batch (section IV.A, as above): plan + run in one call.  The
+ * batch's device memory (descriptors and workspace,
+ * ac_scan_batch_workspace_size bytes) is d_workspace when it is not NULL
+ * (AC_E_OVERFLOW if workspace_bytes is smaller), else it comes from HIP's
+ * stream-ordered allocator and is released when the stream reaches the end
+ * of the batch.  Errors as for ac_scan, checked for every item before
+ * anything is enqueued.  Concurrent calls must not share a workspace. */
+int ac_scan_batch_workspace_size(const ac_batch_item *items, uint32_t n_items,
+                                 const ac_tune *tune, uint64_t *bytes);
 int ac_scan_batch(const ac_batch_item *items, uint32_t n_items, const ac_tune *tune,
-                  void *stream);
+                  void *d_workspace, uint64_t workspace_bytes, void *stream);
+
+/* ---------------------------------------------------------------- serving
+ * A continuous-batching server over device-resident dictionaries: many
+ * independent scans (section IV.A) submitted at any time, grouped into
+ * batches that run on several streams while further requests are admitted.
+ * Requests are DNA letters (ACGT, either case) against one of the server's
+ * dictionaries; each request's matches equal those of ac_scan on its text
+ * alone, in (end_pos, pattern_id) order.
+ *
+ * Threads: ac_server_submit queues a request and returns at once (waiting
+ * only while the pinned staging ring is full); copier threads stage the
+ * letters; a worker admits staged requests while device memory (the budget)
+ * and a free in-flight slot allow, runs each batch (one copy of its letters,
+ * ac_encode, ac_scan_batch, copies of counts and matches back) and hands the
+ * matches to per-request host buffers.  Device memory counted per request:
+ * letters, packed text, reserved matches, count and an upper bound of its
+ * share of the batch workspace.  Matches are reserved from a running
+ * estimate of each dictionary's matches per base; a request whose matches
+ * overflow its reservation is scanned again, alone, exactly sized.  A
+ * request that can never fit the budget is refused (AC_E_NOMEM from
+ * ac_server_wait); letters outside ACGTacgt give AC_E_SYMBOL.  After a HIP
+ * failure every unfinished request gets AC_E_HIP and submits are refused. */
+typedef struct ac_server ac_server;
+
+typedef struct {
+    uint64_t budget_bytes;  /* device memory for requests; 0 = 90% of the free memory
+                               (always capped at that) */
+    uint64_t staging_bytes; /* pinned staging ring for letters; 0 = 256 MiB (a longer
+                               request gets a pinned buffer of its own) */
+    uint32_t max_batch;     /* requests per batch; 0 = 256 (at most 4096) */
+    uint32_t streams;       /* batches in flight; 0 = 4 (at most 16) */
+    uint32_t copy_threads;  /* threads staging letters; 0 = 8 (at most 64) */
+    uint32_t max_wait_us;   /* while batches are in flight, a batch that could grow
+                               waits up to this long for requests being staged */
+    uint32_t fail_batch;    /* fault injection for tests: the k-th batch's device
+                               allocation is reported failed (0 = never) */
+    uint32_t reserved;
+    double margin;          /* reserved matches = margin * (mean + 2 sqrt(mean)) + 64;
+                               negative = 2.0 */
+    ac_tune tune;           /* launch shape of the batches (zeros: library choice) */
+} ac_server_opts;
+
+typedef struct {
+    uint64_t requests;      /* finished successfully */
+    uint64_t bases, matches, batches, reruns;
+    uint64_t overlapped;    /* batches launched while another was in flight */
+    uint64_t peak_bytes;    /* largest device memory counted at once */
+    uint64_t budget_bytes;
+    double wall_s;          /* first submit to last completion */
+    int32_t failed;         /* AC_OK, or the HIP failure that stopped the server */
+    int32_t reserved;
+} ac_server_counters;
+
+/* Create a server over n_dicts dictionaries (sigma 4, with device tables;
+ * they must outlive the server).  Starts its threads. */
+int ac_server_create(ac_dict *const *dicts, uint32_t n_dicts, const ac_server_opts *opts,
+                     ac_server **out);
+/* Queue n letters (host memory; they must stay valid until ac_server_wait
+ * has returned for this request) against dictionary dict_id; *ticket names
+ * the request.  AC_E_INVALID after ac_server_destroy has begun. */
+int ac_server_submit(ac_server *server, const uint8_t *letters, uint64_t n, uint32_t dict_id,
+                     uint64_t *ticket);
+/* Wait for a request (timeout_us < 0: without limit; AC_E_TIMEOUT when it
+ * expires).  On AC_OK, *matches (host memory owned by the server) holds
+ * *count matches until ac_server_release; *latency_s (may be NULL) is the
+ * time from submit to completion.  A failed request returns its code. */
+int ac_server_wait(ac_server *server, uint64_t ticket, int64_t timeout_us,
+                   const ac_match **matches, uint64_t *count, double *latency_s);
+/* Device bytes a request of n letters for dictionary dict_id would be
+ * counted against the budget now (it depends on the running estimate of
+ * matches per base). */
+int ac_server_request_charge(ac_server *server, uint64_t n, uint32_t dict_id, uint64_t *bytes);
+/* Free a finished request's results (AC_E_INVALID while it is pending). */
+int ac_server_release(ac_server *server, uint64_t ticket);
+/* Counters, and up to max_latencies latencies (seconds, completion order). */
+int ac_server_stats(ac_server *server, ac_server_counters *stats, double *latencies,
+                    uint64_t max_latencies);
+/* Finish every queued request, stop the threads, free the server; returns
+ * stats.failed.  NULL is ignored. */
+int ac_server_destroy(ac_server *server);
 
 /* ---------------------------------------------------------------- timing
  * Kernel timing for measurement.  While enabled, every call above records a

@@ -34,6 +34,7 @@ AC_E_NOMEM = -5
 AC_E_OVERFLOW = -6
 AC_E_HIP = -7
 AC_E_NO_DEVICE = -8
+AC_E_TIMEOUT = -9
 
 AC_TEXT_U8 = 0
 AC_TEXT_2BIT = 1
@@ -52,6 +53,8 @@ ABI_SYMBOLS = [
     "ac_batch_destroy", "ac_scan_batch", "ac_status_str", "ac_device_info",
     "ac_timing_enable", "ac_timing_read", "ac_build_partitioned", "ac_dict_parts",
     "ac_scan_pfac", "ac_sort_workspace_size", "ac_sort_matches", "ac_scan_noalloc",
+    "ac_scan_batch_workspace_size", "ac_server_create", "ac_server_submit", "ac_server_wait",
+    "ac_server_release", "ac_server_request_charge", "ac_server_stats", "ac_server_destroy",
 ]
 AC_SORT_BY_END = 1
 AC_NOALLOC_MAX_WORKSPACE = 64 << 20
@@ -105,6 +108,23 @@ class ac_tune(ctypes.Structure):
                 ("chains", ctypes.c_uint32)]
 
 
+class ac_server_opts(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("staging_bytes", ctypes.c_uint64),
+                ("max_batch", ctypes.c_uint32), ("streams", ctypes.c_uint32),
+                ("copy_threads", ctypes.c_uint32), ("max_wait_us", ctypes.c_uint32),
+                ("fail_batch", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("margin", ctypes.c_double), ("tune", ac_tune)]
+
+
+class ac_server_counters(ctypes.Structure):
+    _fields_ = [("requests", ctypes.c_uint64), ("bases", ctypes.c_uint64),
+                ("matches", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("reruns", ctypes.c_uint64), ("overlapped", ctypes.c_uint64),
+                ("peak_bytes", ctypes.c_uint64), ("budget_bytes", ctypes.c_uint64),
+                ("wall_s", ctypes.c_double), ("failed", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
 class ac_batch_item(ctypes.Structure):
     _fields_ = [("dict", ctypes.c_void_p), ("d_text", ctypes.c_void_p), ("n", ctypes.c_uint64),
                 ("fmt", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
@@ -147,6 +167,17 @@ def lib():
     L.ac_scan_workspace_size.restype = i
     L.ac_scan.argtypes = [P, P, u64, u32, P, u64, P, ctypes.POINTER(ac_tune), P, u64, P]
     L.ac_scan.restype = i
+    L.ac_server_create.argtypes = [P, u32, ctypes.POINTER(ac_server_opts), ctypes.POINTER(P)]
+    L.ac_server_submit.argtypes = [P, P, u64, u32, ctypes.POINTER(u64)]
+    L.ac_server_wait.argtypes = [P, u64, ctypes.c_int64, ctypes.POINTER(ctypes.POINTER(ac_match)),
+                                 ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_double)]
+    L.ac_server_release.argtypes = [P, u64]
+    L.ac_server_request_charge.argtypes = [P, u64, u32, ctypes.POINTER(u64)]
+    L.ac_server_stats.argtypes = [P, ctypes.POINTER(ac_server_counters), P, u64]
+    L.ac_server_destroy.argtypes = [P]
+    for name in ("ac_server_create", "ac_server_submit", "ac_server_wait", "ac_server_release",
+                 "ac_server_request_charge", "ac_server_stats", "ac_server_destroy"):
+        getattr(L, name).restype = i
     L.ac_scan_noalloc.argtypes = [P, P, u64, u32, P, u64, P, ctypes.POINTER(ac_tune), P]
     L.ac_scan_noalloc.restype = i
     L.ac_batch_create.argtypes = [ctypes.POINTER(ac_batch_item), u32, ctypes.POINTER(ac_tune),
@@ -156,7 +187,11 @@ def lib():
     L.ac_batch_run.restype = i
     L.ac_batch_destroy.argtypes = [P]
     L.ac_batch_destroy.restype = None
-    L.ac_scan_batch.argtypes = [ctypes.POINTER(ac_batch_item), u32, ctypes.POINTER(ac_tune), P]
+    L.ac_scan_batch.argtypes = [ctypes.POINTER(ac_batch_item), u32, ctypes.POINTER(ac_tune), P,
+                                u64, P]
+    L.ac_scan_batch_workspace_size.argtypes = [ctypes.POINTER(ac_batch_item), u32,
+                                               ctypes.POINTER(ac_tune), ctypes.POINTER(u64)]
+    L.ac_scan_batch_workspace_size.restype = i
     L.ac_scan_batch.restype = i
     L.ac_status_str.argtypes = [i]
     L.ac_status_str.restype = ctypes.c_char_p
@@ -358,11 +393,48 @@ def _items(items) -> Tuple[ctypes.Array, list]:
     return arr, list(items)
 
 
-def ac_scan_batch(items: Sequence[tuple], tune=None, stream=None) -> None:
-    """items: (dict, text_dev, n, fmt, out_dev, capacity, count_dev) tuples."""
+def ac_scan_batch(items: Sequence[tuple], tune=None, stream=None, workspace_dev=None) -> None:
+    """items: (dict, text_dev, n, fmt, out_dev, capacity, count_dev) tuples.
+    workspace_dev: device buffer of ac_scan_batch_workspace_size(items) bytes,
+    or None for the library's stream-ordered allocation."""
     arr, _ = _items(items)
-    _check(lib().ac_scan_batch(arr, len(items), _tune_ref(tune), _stream_ptr(stream)),
+    ws = workspace_dev.data_ptr() if workspace_dev is not None else None
+    wsb = workspace_dev.numel() * workspace_dev.element_size() if workspace_dev is not None else 0
+    _check(lib().ac_scan_batch(arr, len(items), _tune_ref(tune), ws, wsb, _stream_ptr(stream)),
            "ac_scan_batch")
+
+
+def ac_scan_batch_workspace_size(items: Sequence[tuple], tune=None) -> int:
+    arr, _ = _items(items)
+    b = ctypes.c_uint64()
+    _check(lib().ac_scan_batch_workspace_size(arr, len(items), _tune_ref(tune), ctypes.byref(b)),
+           "ac_scan_batch_workspace_size")
+    return b.value
+
+
+# ac_batch_item as a numpy record (same layout as the C struct), so that a
+# caller can fill a whole batch's descriptors with array operations
+BATCH_ITEM_DTYPE = np.dtype([("dict", "<u8"), ("text", "<u8"), ("n", "<u8"), ("fmt", "<u4"),
+                             ("reserved", "<u4"), ("out", "<u8"), ("capacity", "<u8"),
+                             ("count", "<u8")], align=True)
+
+
+def ac_scan_batch_records(records: np.ndarray, tune=None, workspace_ptr=None,
+                          workspace_bytes: int = 0, stream=None) -> None:
+    """ac_scan_batch over a BATCH_ITEM_DTYPE array (device pointers as ints)."""
+    assert records.dtype == BATCH_ITEM_DTYPE and records.flags.c_contiguous
+    _check(lib().ac_scan_batch(records.ctypes.data_as(ctypes.POINTER(ac_batch_item)),
+                               len(records), _tune_ref(tune), workspace_ptr, workspace_bytes,
+                               _stream_ptr(stream)), "ac_scan_batch")
+
+
+def ac_scan_batch_records_workspace_size(records: np.ndarray, tune=None) -> int:
+    assert records.dtype == BATCH_ITEM_DTYPE and records.flags.c_contiguous
+    b = ctypes.c_uint64()
+    _check(lib().ac_scan_batch_workspace_size(
+        records.ctypes.data_as(ctypes.POINTER(ac_batch_item)), len(records), _tune_ref(tune),
+        ctypes.byref(b)), "ac_scan_batch_workspace_size")
+    return b.value
 
 
 def ac_batch_create(items: Sequence[tuple], tune=None) -> "BatchPlan":

@@ -25,7 +25,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = shutil.which("hipcc") or os.path.join(ROCM, "bin", "hipcc")
 ARCH = "gfx950"
 
-HOST_SOURCES = ["automaton.cpp", "api.cpp"]
+HOST_SOURCES = ["automaton.cpp", "api.cpp", "serve.cpp"]
 HIP_SOURCES = ["scan.hip", "sort.hip"]
 MB_SOURCES = ["microbench.hip"]
 DEPS = ["internal.h", "batch.inc", "device_common.h"]

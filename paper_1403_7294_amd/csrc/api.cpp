@@ -1,12 +1,28 @@
 // C-ABI entry points that run on the host only: building, inspecting and
 // releasing dictionaries.  The scan entry points live in scan.hip.
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <new>
 
 #include "internal.h"
+
+namespace acx {
+
+bool test_alloc_fails() {
+    static const long long nth = [] {
+        const char *e = getenv("AC_TEST_FAIL_ALLOC");
+        return e ? atoll(e) : 0LL;
+    }();
+    if (nth <= 0) return false;
+    static std::atomic<long long> seen{0};
+    return ++seen == nth;
+}
+
+}  // namespace acx
 
 extern "C" {
 
@@ -18,7 +34,7 @@ int ac_build(const uint8_t *symbols, const uint64_t *offsets, uint32_t n_pattern
     if (opts) o = *opts;
     if (o.placement > AC_PLACE_LDS2 || (o.flags & ~(AC_BUILD_HOST_ONLY | AC_BUILD_SERIAL)))
         return AC_E_INVALID;
-    ac_dict *d = new (std::nothrow) ac_dict();
+    ac_dict *d = acx::test_alloc_fails() ? nullptr : new (std::nothrow) ac_dict();
     if (!d) return AC_E_NOMEM;
     const auto t0 = std::chrono::steady_clock::now();
     int rc;
@@ -107,7 +123,7 @@ int ac_build_partitioned(const uint8_t *symbols, const uint64_t *offsets, uint32
             ++k;
             continue;
         }
-        ac_dict *d = new (std::nothrow) ac_dict();
+        ac_dict *d = acx::test_alloc_fails() ? nullptr : new (std::nothrow) ac_dict();
         if (!d) {
             for (ac_dict *p : built) ac_destroy(p);
             return AC_E_NOMEM;
@@ -188,6 +204,7 @@ const char *ac_status_str(int s) {
         case AC_E_OVERFLOW: return "workspace too small";
         case AC_E_HIP: return "HIP runtime error";
         case AC_E_NO_DEVICE: return "dictionary has no device tables";
+        case AC_E_TIMEOUT: return "wait timed out";
         default: return "unknown status";
     }
 }

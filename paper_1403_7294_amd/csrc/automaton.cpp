@@ -9,8 +9,9 @@
 //     links from f(r) until a state with an a-edge appears.
 //  3. completed transitions: delta(s, a) = g(s, a) when the edge exists,
 //     otherwise delta(f(s), a) (delta(0, a) = 0 without an edge).  Reading a
-//     symbol is then one table lookup, which is what the paper's failure
-//     loop ("read the same input character again") amounts to.
+//     symbol is then one table lookup, which is what the failure loop of
+//     section III.A (take failure transitions, then retry the symbol)
+//     amounts to.
 //  4. output sets: out(s) = keywords ending at s plus out(f(s)), ids sorted.
 //  5. renumbering: root 0, then output-free states from most to least
 //     likely to be visited, then output states in breadth-first order.  The
@@ -34,6 +35,7 @@
 #include <condition_variable>
 #include <functional>
 #include <mutex>
+#include <new>
 #include <thread>
 #include <vector>
 
@@ -155,6 +157,9 @@ int compile_automaton(const uint8_t *symbols, const uint64_t *offsets, uint32_t 
     };
 
     // ---- 1. trie (goto function); -1 = no edge
+    // (each phase's allocations may be failed by the test hook: the caller
+    // turns std::bad_alloc into AC_E_NOMEM, and every vector is released)
+    if (test_alloc_fails()) throw std::bad_alloc();
     std::vector<int32_t> child;
     child.reserve((size_t)(total + 1) * sigma);
     child.assign(sigma, -1);
@@ -178,6 +183,7 @@ int compile_automaton(const uint8_t *symbols, const uint64_t *offsets, uint32_t 
     const uint32_t S = (uint32_t)depth.size();
 
     // ---- 2./3. breadth-first levels, failure links and completed rows
+    if (test_alloc_fails()) throw std::bad_alloc();
     std::vector<uint32_t> bfs(S);
     std::vector<uint32_t> level_begin{0, 1};  // level d = bfs[level_begin[d] .. level_begin[d+1])
     bfs[0] = 0;
@@ -226,6 +232,7 @@ int compile_automaton(const uint8_t *symbols, const uint64_t *offsets, uint32_t 
     const size_t levels = level_begin.size() - 2;
 
     // ---- 4. output sets, level by level (f(s) is shallower than s)
+    if (test_alloc_fails()) throw std::bad_alloc();
     std::vector<uint32_t> own_cnt(S + 1, 0);
     for (uint32_t i = 0; i < n_patterns; ++i) own_cnt[end_state[i] + 1]++;
     for (uint32_t s = 0; s < S; ++s) own_cnt[s + 1] += own_cnt[s];
@@ -277,6 +284,7 @@ int compile_automaton(const uint8_t *symbols, const uint64_t *offsets, uint32_t 
     }
 
     // ---- 5. renumbering
+    if (test_alloc_fails()) throw std::bad_alloc();
     std::vector<double> logp_sym(sigma, 0.0);
     {
         std::vector<uint64_t> freq(sigma, 1);  // add-one smoothing
@@ -343,6 +351,7 @@ int compile_automaton(const uint8_t *symbols, const uint64_t *offsets, uint32_t 
     T.min_len = min_len;
     T.max_len = max_len;
     T.first_output = first_output;
+    if (test_alloc_fails()) throw std::bad_alloc();
     T.delta.assign((size_t)S * sigma, 0);
     T.depth.assign(S, 0);
     parallel_for(threads, S, [&](size_t k0, size_t k1) {

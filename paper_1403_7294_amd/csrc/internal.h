@@ -52,6 +52,13 @@ struct RowDiv {
 };
 RowDiv make_row_div(uint32_t sigma);
 
+// Allocation-failure injection for tests: with AC_TEST_FAIL_ALLOC=<n> in the
+// environment, the n-th allocation the library checks (counted from 1 over
+// the life of the process) is reported as failed, and the caller takes the
+// same path as for a real failure (AC_E_NOMEM, everything released).
+// Without the variable it is always false.
+bool test_alloc_fails();
+
 }  // namespace acx
 
 struct ihipStream_t;

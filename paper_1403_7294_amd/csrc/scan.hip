@@ -1715,7 +1715,7 @@ int upload_dict(ac_dict *d) {
         }
     }
     const size_t ids_bytes = std::max<size_t>(4, T.out_ids.size() * 4);
-    if (hipMalloc((void **)&d->d_delta, rows.size() * 4) != hipSuccess ||
+    if (test_alloc_fails() || hipMalloc((void **)&d->d_delta, rows.size() * 4) != hipSuccess ||
         hipMalloc((void **)&d->d_out_off, off_bytes) != hipSuccess ||
         hipMalloc((void **)&d->d_out_ids, ids_bytes) != hipSuccess ||
         hipMalloc((void **)&d->d_out_size, sizes.size() * 4) != hipSuccess ||
@@ -2325,7 +2325,7 @@ int ac_scan(const ac_dict *d, const void *d_text, uint64_t n, uint32_t fmt, ac_m
     if (ws) {
         if (workspace_bytes < need) return AC_E_OVERFLOW;
     } else {
-        if (hipMallocAsync((void **)&ws, need, st) != hipSuccess) {
+        if (test_alloc_fails() || hipMallocAsync((void **)&ws, need, st) != hipSuccess) {
             (void)hipGetLastError();
             return AC_E_NOMEM;
         }

@@ -1,47 +1,32 @@
 """Continuous-batching server for Aho-Corasick scans on one GPU.
 
-Requests (a text as letters, and the index of one of the server's
-device-resident dictionaries) arrive at any time through ``submit``.  A
-worker thread admits waiting requests while the device-memory budget and the
-batch slots allow, packs them into one batch, and runs the batch on one of
-several streams: host-to-device copy of the letters, ``ac_encode`` into
-2-bit text, ``ac_scan_batch`` over all requests of the batch, copy of the
-matches back.  Requests that arrive while batches are running are admitted
-into the next batch at once, so their work overlaps the batches already on
-the GPU; memory is released, and further requests admitted, as batches
-complete.  Each request's future resolves to its matches (uint64 keys
-``end << 32 | pattern_id`` in (end, id) order) - the same result the request
-would get from a scan alone.
+Python face of the library's serving core (``ac_server_*`` in the C ABI,
+``csrc/serve.cpp``).  Requests - a text as letters and the index of one of
+the server's device-resident dictionaries - arrive at any time through
+``submit``; the core stages their letters in a pinned ring, admits them into
+batches while device memory and an in-flight slot allow, runs each batch as
+one set of independent scans (the paper's section IV.A) on one of several
+streams, so that requests arriving while batches run are admitted at once
+and overlap them on the GPU, and hands each request its matches.  A
+request's result is its matches as uint64 keys ``end << 32 | pattern_id`` in
+(end, id) order: the same as a scan of its text alone.
 
-Output space is reserved per request from a running estimate of the
-dictionary's matches per base; a request whose matches overflow its
-reservation is scanned again, alone, with an exact-size buffer.
+Queueing, staging, admission, launches and completion all run in the
+core's native threads; this module only marshals arguments, so a request
+costs the submitting thread one library call and its result one more.
 """
 from __future__ import annotations
 
-import collections
 import concurrent.futures
+import ctypes
 import dataclasses
-import threading
 import time
 from typing import List, Optional, Sequence
 
 import numpy as np
 
-from . import (AC_ALPHA_DNA, AC_TEXT_2BIT, ac_build, ac_encode, ac_scan, ac_scan_batch,
-               match_keys)
-
-
-@dataclasses.dataclass
-class _Request:
-    rid: int
-    dict_id: int
-    letters: np.ndarray
-    arrival: float
-    future: concurrent.futures.Future
-    capacity: int = 0
-    nbytes: int = 0
-    done: float = 0.0
+from . import (AC_E_HIP, AC_E_NOMEM, AC_E_SYMBOL, AC_E_TIMEOUT, AC_OK, ACError, ac_build,
+               ac_match, ac_server_counters, ac_server_opts, ac_tune, lib)
 
 
 @dataclasses.dataclass
@@ -54,6 +39,7 @@ class ServeStats:
     wall_s: float
     peak_bytes: int
     overlapped: int = 0   # batches launched while another was in flight
+    budget_bytes: int = 0
 
     def summary(self) -> dict:
         lat = np.array(self.latencies_s) if self.latencies_s else np.zeros(1)
@@ -67,246 +53,178 @@ class ServeStats:
                 if self.wall_s else 0.0,
                 "matches": self.matches, "batches": self.batches, "reruns": self.reruns,
                 "overlapped_batches": self.overlapped,
-                "peak_device_bytes": self.peak_bytes}
+                "peak_device_bytes": self.peak_bytes, "budget_bytes": self.budget_bytes}
+
+
+def _error(rc: int) -> Exception:
+    if rc == AC_E_NOMEM:
+        return MemoryError("request larger than the server's memory budget")
+    if rc == AC_E_SYMBOL:
+        return ValueError("request text has letters outside ACGTacgt")
+    if rc == AC_E_HIP:
+        return RuntimeError("server worker failed")
+    return ACError(rc, "ac_server_wait")
+
+
+class ServeFuture:
+    """One request's result.  ``result()`` waits for it inside the library
+    (without holding the interpreter lock); ``done()`` does not wait."""
+
+    def __init__(self, server: "Server", ticket: int, letters: np.ndarray):
+        self._srv = server
+        self._ticket = ticket
+        self._letters = letters      # the core reads them until they are staged
+        self._done = False
+        self._res: Optional[np.ndarray] = None
+        self._exc: Optional[BaseException] = None
+        self.latency_s = 0.0
+
+    def _fetch(self, timeout_us: int) -> bool:
+        L = lib()
+        ptr = ctypes.POINTER(ac_match)()
+        cnt = ctypes.c_uint64()
+        lat = ctypes.c_double()
+        rc = L.ac_server_wait(self._srv._h, self._ticket, timeout_us, ctypes.byref(ptr),
+                              ctypes.byref(cnt), ctypes.byref(lat))
+        if rc == AC_E_TIMEOUT:
+            return False
+        if rc == AC_OK:
+            n = cnt.value
+            if n:
+                m = np.ctypeslib.as_array(ctypes.cast(ptr, ctypes.POINTER(ctypes.c_uint32)),
+                                          shape=(n, 2))
+                self._res = ((m[:, 1].astype(np.uint64) << np.uint64(32)) |
+                             m[:, 0].astype(np.uint64))
+            else:
+                self._res = np.zeros(0, dtype=np.uint64)
+        else:
+            self._exc = _error(rc)
+        self.latency_s = lat.value
+        L.ac_server_release(self._srv._h, self._ticket)
+        self._letters = None
+        self._done = True
+        return True
+
+    def result(self, timeout: Optional[float] = None):
+        if not self._done and not self._fetch(-1 if timeout is None else int(timeout * 1e6)):
+            raise concurrent.futures.TimeoutError()
+        if self._exc is not None:
+            raise self._exc
+        return self._res
+
+    def done(self) -> bool:
+        return self._done or self._fetch(0)
 
 
 class Server:
     """Serve scans of DNA texts against dictionaries kept on the GPU.
 
-    dictionaries  list of pattern sets (code lists or CSR objects), DNA codes
-    budget_bytes  device memory the server may hold for requests at once
-    max_batch     requests per batch
-    streams       batches in flight at once (>= 2 to overlap)
+    dictionaries   list of pattern sets (code lists or CSR objects), DNA codes
+    budget_bytes   device memory the server may hold for requests at once
+                   (capped by the device's free memory at construction)
+    max_batch      requests per batch
+    streams        batches in flight at once (>= 2 to overlap)
+    staging_bytes  pinned staging ring for letters
+    copy_threads   threads that stage letters
+    max_wait_us    how long a batch that could grow waits for requests being
+                   staged while other batches are in flight
+    margin         reserved matches = margin * (mean + 2 sqrt(mean)) + 64
+    tune           launch shape of the batches (dict or ac_tune)
+    fail_batch     fault injection for tests: the k-th batch's device
+                   allocation is reported failed
     """
 
     def __init__(self, dictionaries: Sequence, budget_bytes: int = 4 << 30,
-                 max_batch: int = 64, streams: int = 2, tune=None,
-                 margin: float = 2.0):
-        import torch
-        self.torch = torch
-        self.dev = torch.device("cuda", torch.cuda.current_device())
+                 max_batch: int = 256, streams: int = 4, tune=None, margin: float = 2.0,
+                 staging_bytes: int = 256 << 20, copy_threads: int = 8,
+                 max_wait_us: int = 200, fail_batch: int = 0):
+        self._h = None
         self.dicts = [ac_build(p, sigma=4) for p in dictionaries]
-        self.budget = int(budget_bytes)
-        self.max_batch = int(max_batch)
-        self.streams = [torch.cuda.Stream(self.dev) for _ in range(max(2, streams))]
-        self.tune = tune
-        self.margin = margin
-        # matches per base, per dictionary (running estimate)
-        self.rate = [1e-3] * len(self.dicts)
-        self._q: collections.deque = collections.deque()
-        self._cv = threading.Condition()
-        self._closing = False
-        self._next_id = 0
-        self._used = 0
-        self._peak = 0
-        self._lat: List[float] = []
-        self._bases = 0
-        self._matches = 0
-        self._batches = 0
-        self._reruns = 0
-        self._overlapped = 0
-        self._t0: Optional[float] = None
-        self._t_last = 0.0
-        self._err: Optional[BaseException] = None
-        self._worker = threading.Thread(target=self._run, name="ac-serve", daemon=True)
-        self._worker.start()
+        t = ac_tune()
+        if isinstance(tune, ac_tune):
+            t = tune
+        elif tune:
+            t = ac_tune(tune.get("chunk", 0), tune.get("block_threads", 0),
+                        tune.get("placement", 0), tune.get("blocks_per_cu", 0),
+                        tune.get("chains", 0))
+        o = ac_server_opts(int(budget_bytes), int(staging_bytes), int(max_batch), int(streams),
+                           int(copy_threads), int(max_wait_us), int(fail_batch), 0,
+                           float(margin), t)
+        arr = (ctypes.c_void_p * len(self.dicts))(*[d.handle.value for d in self.dicts])
+        h = ctypes.c_void_p()
+        rc = lib().ac_server_create(arr, len(self.dicts), ctypes.byref(o), ctypes.byref(h))
+        if rc != AC_OK:
+            raise ACError(rc, "ac_server_create")
+        self._h = h
+        self._futs: List[ServeFuture] = []
+        c = ac_server_counters()
+        lib().ac_server_stats(self._h, ctypes.byref(c), None, 0)
+        self.budget = c.budget_bytes
 
-    # ------------------------------------------------------------ client API
-
-    def submit(self, letters: np.ndarray, dict_id: int) -> concurrent.futures.Future:
+    def submit(self, letters: np.ndarray, dict_id: int) -> ServeFuture:
         """Queue a text (uint8 ASCII letters ACGT) for a scan against
         dictionary dict_id.  Returns a future of the uint64 match keys."""
         if not 0 <= dict_id < len(self.dicts):
             raise ValueError("no such dictionary")
-        f: concurrent.futures.Future = concurrent.futures.Future()
+        if self._h is None:
+            raise RuntimeError("server closed")
         letters = np.ascontiguousarray(letters, dtype=np.uint8)
-        with self._cv:
-            if self._closing:
-                raise RuntimeError("server closed")
-            r = _Request(self._next_id, dict_id, letters, time.perf_counter(), f)
-            self._next_id += 1
-            self._size(r)
-            if r.nbytes > self.budget:
-                f.set_exception(MemoryError("request larger than the server's memory budget"))
-                return f
-            if self._t0 is None:
-                self._t0 = r.arrival
-            self._q.append(r)
-            self._cv.notify()
+        ticket = ctypes.c_uint64()
+        rc = lib().ac_server_submit(self._h, letters.ctypes.data if len(letters) else None,
+                                    len(letters), dict_id, ctypes.byref(ticket))
+        if rc == AC_E_HIP:
+            raise RuntimeError("server worker failed")
+        if rc != AC_OK:
+            raise ACError(rc, "ac_server_submit")
+        f = ServeFuture(self, ticket.value, letters)
+        self._futs.append(f)
         return f
 
+    def request_charge(self, n: int, dict_id: int) -> int:
+        """Device bytes a request of n letters for dictionary dict_id would be
+        counted against the budget now."""
+        b = ctypes.c_uint64()
+        rc = lib().ac_server_request_charge(self._h, n, dict_id, ctypes.byref(b))
+        if rc != AC_OK:
+            raise ACError(rc, "ac_server_request_charge")
+        return b.value
+
+    def _drain(self):
+        for f in self._futs:
+            if not f._done:
+                f._fetch(-1)
+        self._futs = []
+
     def close(self) -> ServeStats:
-        """Finish every queued request and stop the worker."""
-        with self._cv:
-            self._closing = True
-            self._cv.notify()
-        self._worker.join()
-        if self._err is not None:
-            raise self._err
-        wall = (self._t_last - self._t0) if self._t0 is not None else 0.0
-        return ServeStats(self._lat, self._bases, self._matches, self._batches, self._reruns,
-                          wall, self._peak, self._overlapped)
+        """Finish every queued request (their futures keep their results)
+        and stop the server."""
+        if self._h is None:
+            raise RuntimeError("server closed")
+        self._drain()
+        c = ac_server_counters()
+        L = lib()
+        L.ac_server_stats(self._h, ctypes.byref(c), None, 0)
+        lat = np.zeros(max(1, c.requests), dtype=np.float64)
+        L.ac_server_stats(self._h, ctypes.byref(c), lat.ctypes.data, c.requests)
+        failed = L.ac_server_destroy(self._h)
+        self._h = None
+        if failed != AC_OK:
+            raise RuntimeError("server worker failed")
+        return ServeStats(lat[:c.requests].tolist(), c.bases, c.matches, c.batches, c.reruns,
+                          c.wall_s, c.peak_bytes, c.overlapped, c.budget_bytes)
 
-    # ------------------------------------------------------------ internals
-
-    def _size(self, r: _Request):
-        n = len(r.letters)
-        est = int(self.rate[r.dict_id] * n * self.margin) + 64
-        r.capacity = est
-        # letters (padded) + packed text + matches + count
-        r.nbytes = _pad16(n) + _pad16(n) // 4 + 8 * est + 8
-
-    def _take(self, n_inflight: int) -> List[_Request]:
-        """Admit queued requests in arrival order while memory and slots allow
-        (caller holds the lock)."""
-        batch: List[_Request] = []
-        if n_inflight >= len(self.streams):
-            return batch
-        while (self._q and len(batch) < self.max_batch and
-               self._used + self._q[0].nbytes <= self.budget):
-            r = self._q.popleft()
-            self._used += r.nbytes
-            batch.append(r)
-        self._peak = max(self._peak, self._used)
-        return batch
-
-    def _run(self):
+    def __del__(self):
         try:
-            inflight: collections.deque = collections.deque()
-            k = 0
-            while True:
-                while inflight and inflight[0]["event"].query():
-                    self._finish(inflight.popleft())
-                with self._cv:
-                    batch = self._take(len(inflight))
-                    if not batch:
-                        if not inflight:
-                            if self._closing and not self._q:
-                                return
-                            self._cv.wait(timeout=0.05)
-                            continue
-                        blocked = bool(self._q)  # slots or memory exhausted
-                        if not blocked:
-                            # wait for an arrival, then look at the GPU again
-                            self._cv.wait(timeout=2e-4)
-                            continue
-                if not batch:
-                    self._finish(inflight.popleft())  # blocks on the oldest batch
-                    continue
-                st = self.streams[k % len(self.streams)]
-                k += 1
-                if inflight:
-                    self._overlapped += 1
-                inflight.append(self._launch(batch, st))
-        except BaseException as e:  # surface worker failures to close()
-            self._err = e
-            with self._cv:
-                for r in self._q:
-                    r.future.set_exception(e)
-                self._q.clear()
-
-    def _launch(self, batch: List[_Request], st) -> dict:
-        torch = self.torch
-        offs = np.zeros(len(batch) + 1, dtype=np.int64)
-        for i, r in enumerate(batch):
-            offs[i + 1] = offs[i] + _pad16(len(r.letters))
-        host = torch.empty(int(offs[-1]), dtype=torch.uint8, pin_memory=True)
-        hv = host.numpy()
-        hv[:] = ord("A")
-        for i, r in enumerate(batch):
-            hv[offs[i]:offs[i] + len(r.letters)] = r.letters
-        caps = np.array([r.capacity for r in batch], dtype=np.int64)
-        moff = np.zeros(len(batch) + 1, dtype=np.int64)
-        np.cumsum(caps, out=moff[1:])
-        with torch.cuda.stream(st):
-            letters = torch.empty(int(offs[-1]), dtype=torch.uint8, device=self.dev)
-            letters.copy_(host, non_blocking=True)
-            packed = torch.empty(int(offs[-1]) // 4, dtype=torch.uint8, device=self.dev)
-            bad = torch.zeros(1, dtype=torch.int64, device=self.dev)
-            ac_encode(letters, AC_ALPHA_DNA, AC_TEXT_2BIT, packed, bad, stream=st)
-            out = torch.empty((int(moff[-1]), 2), dtype=torch.int32, device=self.dev)
-            counts = torch.zeros(len(batch), dtype=torch.int64, device=self.dev)
-            items = []
-            for i, r in enumerate(batch):
-                t = packed[offs[i] // 4:offs[i + 1] // 4]
-                items.append((self.dicts[r.dict_id], t, len(r.letters), AC_TEXT_2BIT,
-                              out[moff[i]:moff[i + 1]], int(caps[i]), counts[i:i + 1]))
-            ac_scan_batch(items, tune=self.tune, stream=st)
-            counts_host = torch.empty(len(batch) + 1, dtype=torch.int64, pin_memory=True)
-            counts_host[:len(batch)].copy_(counts, non_blocking=True)
-            counts_host[len(batch):].copy_(bad, non_blocking=True)
-            # the reserved output comes back in one copy; the host reads what
-            # each request filled once the batch is done
-            out_host = torch.empty(out.shape, dtype=torch.int32, pin_memory=True)
-            out_host.copy_(out, non_blocking=True)
-            ev = torch.cuda.Event()
-            ev.record(st)
-        return {"batch": batch, "stream": st, "event": ev, "out": out, "moff": moff,
-                "counts": counts_host, "out_host": out_host, "packed": packed, "offs": offs, "keep": (host, letters)}
-
-    def _finish(self, b: dict):
-        torch = self.torch
-        b["event"].synchronize()
-        counts = b["counts"].numpy()
-        batch: List[_Request] = b["batch"]
-        st = b["stream"]
-        results: list = []
-        invalid = counts[len(batch)] != 0
-        with torch.cuda.stream(st):
-            for i, r in enumerate(batch):
-                c = int(counts[i])
-                if invalid and not _dna_letters(r.letters):
-                    # the encoder counted letters outside ACGTacgt in this batch
-                    results.append(ValueError("request text has letters outside ACGTacgt"))
-                elif c <= r.capacity:
-                    m = b["out_host"][b["moff"][i]:b["moff"][i] + c]
-                    results.append(match_keys(m))
-                else:
-                    # overflow: scan this request again, alone, exactly sized
-                    self._reruns += 1
-                    t = b["packed"][b["offs"][i] // 4:b["offs"][i + 1] // 4]
-                    o = torch.empty((c, 2), dtype=torch.int32, device=self.dev)
-                    cnt = torch.zeros(1, dtype=torch.int64, device=self.dev)
-                    ac_scan(self.dicts[r.dict_id], t, len(r.letters), AC_TEXT_2BIT, o, c, cnt,
-                            tune=self.tune, stream=st)
-                    st.synchronize()
-                    results.append(match_keys(o))
-        now = time.perf_counter()
-        with self._cv:
-            for r, res in zip(batch, results):
-                self._used -= r.nbytes
-                if isinstance(res, Exception):
-                    continue
-                n = len(r.letters)
-                if n:
-                    self.rate[r.dict_id] = 0.8 * self.rate[r.dict_id] + 0.2 * (len(res) / n)
-                self._lat.append(now - r.arrival)
-                self._bases += n
-                self._matches += len(res)
-            self._batches += 1
-            self._t_last = now
-            self._cv.notify()
-        for r, res in zip(batch, results):
-            if isinstance(res, Exception):
-                r.future.set_exception(res)
-            else:
-                r.future.set_result(res)
-
-
-def _pad16(n: int) -> int:
-    return (n + 15) // 16 * 16
-
-
-_DNA_OK = np.zeros(256, dtype=bool)
-_DNA_OK[np.frombuffer(b"ACGTacgt", dtype=np.uint8)] = True
-
-
-def _dna_letters(letters: np.ndarray) -> bool:
-    return bool(_DNA_OK[letters].all())
+            if self._h is not None:
+                self._drain()
+                lib().ac_server_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
 
 
 def run_poisson(server: Server, texts: Sequence[np.ndarray], dict_of: Sequence[int],
-                gaps: Sequence[float], rate: float) -> List[concurrent.futures.Future]:
+                gaps: Sequence[float], rate: float) -> List[ServeFuture]:
     """Submit texts at Poisson arrival times (gaps are Exp(1) draws scaled
     by 1/rate requests per second), from the calling thread."""
     futs = []

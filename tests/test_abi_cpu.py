@@ -224,3 +224,12 @@ def test_microbench_cycle_is_one_permutation_cycle():
         if s == 0:
             break
     assert seen == 4096
+
+
+def test_batch_item_record_layout_matches_the_c_struct():
+    import ctypes as C
+    dt = ac.BATCH_ITEM_DTYPE
+    assert dt.itemsize == C.sizeof(ac.ac_batch_item)
+    for name, ctype in ac.ac_batch_item._fields_:
+        rec = {"d_text": "text", "d_out": "out", "d_count": "count"}.get(name, name)
+        assert dt.fields[rec][1] == getattr(ac.ac_batch_item, name).offset, name

@@ -94,3 +94,27 @@ def test_hybrid_overflow_writes_nothing_past_capacity():
         assert int(cnt.item()) == len(want)
         assert np.array_equal(ac.match_keys(out[:cap]), want[:cap])
         assert (out[cap:] == -1).all()
+
+
+@pytest.mark.parametrize("hot", [0, 50, 2000])
+def test_hybrid_walk_long_patterns(hot):
+    # patterns of 34-200 bases: the warm-up before each chunk spans more
+    # than two 16-base text words, the walk's other warm-up path; chunks of
+    # 64 are shorter than the longest pattern
+    rng = W.rng_for(900 + hot)
+    n = 120_007
+    text = rng.integers(0, 4, size=n, dtype=np.uint8)
+    for start in range(100, n - 300, 9000):
+        text[start:start + int(rng.integers(40, 260))] = 0
+    pats = W._cut(rng, text, rng.integers(34, 201, size=120))
+    pats += [np.zeros(k, np.uint8) for k in (34, 40, 64, 100, 200)]
+    pats += [rng.integers(0, 4, size=int(L), dtype=np.uint8) for L in rng.integers(34, 80, size=60)]
+    pats += W._cut(rng, text, rng.integers(6, 12, size=40))      # short ones too
+    inst = W.Instance(text, W.PatternSet.from_list(pats), 4, W.DNA, "long")
+    d = ac.ac_build(inst.patterns, sigma=4, hot_states=hot)
+    assert d.info.max_len >= 34
+    for chains in (1, 2, 4):
+        for chunk in (64, 256):
+            tune = {"placement": ac.AC_PLACE_HYBRID, "chains": chains, "chunk": chunk}
+            _say("long patterns, hot rows", hot, "tune", tune)
+            _check(inst, d, tune)

@@ -95,7 +95,9 @@ def test_serve_memory_budget():
     pats, texts, dict_of, _ = _workload(13, 40)
     want = _expected(pats, texts, dict_of)
     big = max(len(t) for t in texts)
-    budget = 3 * (big + big // 4 + 8 * (big // 100 + 64) + 64)
+    probe = Server(pats)
+    budget = 3 * max(probe.request_charge(big, d) for d in range(len(pats)))
+    probe.close()
     srv = Server(pats, budget_bytes=budget, max_batch=64, streams=2)
     futs = [srv.submit(_letters(t), int(d)) for t, d in zip(texts, dict_of)]
     got = [f.result(timeout=60) for f in futs]
@@ -128,4 +130,46 @@ def test_serve_invalid_letters_and_empty():
     assert len(empty.result(timeout=60)) == 0
     for k, (f, w) in enumerate(zip(good, want)):
         assert np.array_equal(f.result(timeout=60), w), k
+    srv.close()
+
+
+def test_serve_failed_batch_allocation():
+    # the third batch's device allocation is reported failed (fault
+    # injection from the host; no GPU fault): exactly that batch's requests
+    # get MemoryError, every other request is served correctly, and the
+    # server keeps going
+    torch_cuda()
+    from paper_1403_7294_amd.serve import Server
+    pats, texts, dict_of, _ = _workload(15, 40)
+    want = _expected(pats, texts, dict_of)
+    srv = Server(pats, max_batch=4, streams=2, fail_batch=3)
+    futs = [srv.submit(_letters(t), int(d)) for t, d in zip(texts, dict_of)]
+    failed = 0
+    for k, (f, w) in enumerate(zip(futs, want)):
+        try:
+            got = f.result(timeout=60)
+        except MemoryError:
+            failed += 1
+            continue
+        assert np.array_equal(got, w), k
+    assert 1 <= failed <= 4
+    late = srv.submit(_letters(texts[0]), int(dict_of[0]))
+    assert np.array_equal(late.result(timeout=60), want[0])
+    st = srv.close()
+    assert len(st.latencies_s) == len(texts) - failed + 1
+
+
+def test_serve_accounts_batch_workspace():
+    # the budget counts each request's share of the batch workspace: a
+    # budget just above one request's letters, text and reservation, but
+    # below that plus its workspace bound, refuses it
+    torch_cuda()
+    from paper_1403_7294_amd.serve import Server
+    pats, texts, dict_of, _ = _workload(16, 8)
+    n = 100_000
+    srv = Server(pats, budget_bytes=n + n // 4 + 8 * 300 + 4096)
+    assert srv.request_charge(n, 0) > 1.5 * n + n + n // 4
+    f = srv.submit(_letters(np.zeros(n, np.uint8)), 0)
+    with pytest.raises(MemoryError):
+        f.result(timeout=10)
     srv.close()
