@@ -99,11 +99,16 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the partitioned / failure-less / two-symbol comparisons")
+    ap.add_argument("--no-protein", action="store_true", help="skip the protein workload")
+    ap.add_argument("--no-small", action="store_true", help="skip the dna_small graph loop")
     ap.add_argument("--no-peaks", action="store_true",
                     help="skip the microbenchmarks of the HBM, LDS and gather ceilings")
     ap.add_argument("--serve-requests", type=int, default=10_000,
                     help="requests timed at the fixed arrival rate")
     ap.add_argument("--scale", type=float, default=1.0, help="shrink the workload (testing)")
+    ap.add_argument("--profile-leg", choices=["protein", "batch", "dna_small"], default=None,
+                    help="run only this workload's leg and print its JSON (for kernel traces "
+                         "of one workload under rocprofv3); no benchmark line")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB device to device 5 times: the reference kernel that "
                          "scales the FETCH_SIZE / WRITE_SIZE counters to bytes")
@@ -129,6 +134,13 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "device copy", "bytes_read": 1 << 30,
                           "bytes_written": 1 << 30, "launches": 5}), flush=True)
+        return
+
+    if args.profile_leg:
+        leg = {"protein": lambda: bench_protein(args, torch, ac, W, dev, stream),
+               "batch": lambda: bench_batch(args, torch, ac, W, dev, stream),
+               "dna_small": lambda: bench_small_graph(args, torch, ac, W, dev, stream)}
+        print(json.dumps({args.profile_leg: leg[args.profile_leg]()}), flush=True)
         return
 
     t0 = time.time()
@@ -341,8 +353,10 @@ def main():
                                             scan_ms)
 
     # --------------------------------------------------------- other configs
-    result["protein"] = bench_protein(args, torch, ac, W, dev, stream)
-    result["dna_small_graph"] = bench_small_graph(args, torch, ac, W, dev, stream)
+    if not args.no_protein:
+        result["protein"] = bench_protein(args, torch, ac, W, dev, stream)
+    if not args.no_small:
+        result["dna_small_graph"] = bench_small_graph(args, torch, ac, W, dev, stream)
     if not args.no_peaks:
         result["measured_peaks"] = bench_peaks(torch, result)
 
@@ -626,8 +640,17 @@ def bench_batch(args, torch, ac, W, dev, stream):
     plan2.close()
     same_two = all(np.array_equal(ac.match_keys(o[:int(c)]), k)
                    for o, c, k in zip(outs, caps, plain_keys))
+    # the launch shape picked by the autotuner for this batch
+    from paper_1403_7294_amd import tune as actune
+    best = actune.autotune_batch(items)
+    plan3 = ac.ac_batch_create(items, tune=best)
+    tuned_ms = timeit(lambda: ac.ac_batch_run(plan3), reps)
+    plan3.close()
+    same_tuned = all(np.array_equal(ac.match_keys(o[:int(c)]), k)
+                     for o, c, k in zip(outs, caps, plain_keys))
     log(f"[bench] batch: plain {plain_ms:.3f} ms, batched {batch_ms:.3f} ms, "
-        f"graph {graph_ms:.3f} ms, identical {same and same_graph}")
+        f"graph {graph_ms:.3f} ms, autotuned {tuned_ms:.3f} ms ({best}), "
+        f"identical {same and same_graph and same_tuned}")
     plan.close()
     return {"workload": "batch: 512 DNA instances, text log-uniform 4 Ki-4 Mi bases, "
                         "10-2,000 patterns of 8-24 each, 2-bit text",
@@ -639,7 +662,9 @@ def bench_batch(args, torch, ac, W, dev, stream):
             "speedup_batched_vs_plain": round(plain_ms / batch_ms, 2),
             "speedup_graph_vs_plain": round(plain_ms / graph_ms, 2),
             "two_symbol_batched_ms": round(two_ms, 3),
-            "identical_to_plain": bool(same and same_graph and same_two)}
+            "autotuned_ms": round(tuned_ms, 3), "autotuned_shape": best,
+            "autotuned_gbases_s": round(bases / (tuned_ms * 1e-3) / 1e9, 3),
+            "identical_to_plain": bool(same and same_graph and same_two and same_tuned)}
 
 
 def _timed(torch, fn, reps):

@@ -15,9 +15,11 @@
 //  4. output sets: out(s) = keywords ending at s plus out(f(s)), ids sorted.
 //  5. renumbering: root 0, then output-free states from most to least
 //     likely to be visited, then output states in breadth-first order.  The
-//     visit likelihood of a state is estimated as the probability of its
-//     string under independent symbols with the frequencies of the pattern
-//     symbols; the scan keeps the first rows of the table in LDS (and, in
+//     visit probability of a state is the chance that the walk sits in it
+//     when the text has independent symbols with the frequencies of the
+//     pattern symbols (its string's probability less that of the strings
+//     whose failure link points straight to it); the scan keeps the first
+//     rows of the table in LDS (and, in
 //     16-bit form, rows whose targets are among the first 65,535 states).
 //     Only the first 65,536 output-free states are ranked this way; any
 //     further ones follow in breadth-first order.
@@ -285,14 +287,24 @@ int compile_automaton(const uint8_t *symbols, const uint64_t *offsets, uint32_t 
 
     // ---- 5. renumbering
     if (test_alloc_fails()) throw std::bad_alloc();
-    std::vector<double> logp_sym(sigma, 0.0);
+    // Visit probability of each state under text drawn i.i.d. from the
+    // patterns' symbol frequencies: the walk is in s exactly when the text
+    // read so far ends with s's string but with no longer trie string, and
+    // the longer trie strings that end with s's string and fail straight to
+    // s are disjoint events, so P(s) = p(s) - sum of p(t) over the states t
+    // with f(t) = s, where p(x) is the probability of x's string.  Shallow
+    // states with every one-symbol extension in the trie are never entered
+    // after the first few symbols and rank low; the states the walk really
+    // sits in rank high.
+    std::vector<double> p_sym(sigma, 0.0);
     {
         std::vector<uint64_t> freq(sigma, 1);  // add-one smoothing
         for (uint64_t k = 0; k < total; ++k) freq[symbols[k]]++;
         const double all = (double)(total + sigma);
-        for (uint32_t a = 0; a < sigma; ++a) logp_sym[a] = std::log((double)freq[a] / all);
+        for (uint32_t a = 0; a < sigma; ++a) p_sym[a] = (double)freq[a] / all;
     }
-    std::vector<double> logp(S, 0.0);
+    std::vector<double> pstr(S, 0.0);
+    pstr[0] = 1.0;
     for (size_t d = 0; d < levels; ++d) {
         const uint32_t b = level_begin[d], e = level_begin[d + 1];
         parallel_for(threads, e - b, [&](size_t i0, size_t i1) {
@@ -300,14 +312,14 @@ int compile_automaton(const uint8_t *symbols, const uint64_t *offsets, uint32_t 
                 const uint32_t s = bfs[b + i];
                 for (uint32_t a = 0; a < sigma; ++a) {
                     const int32_t t = child[(size_t)s * sigma + a];
-                    if (t >= 0) logp[t] = logp[s] + logp_sym[a];
+                    if (t >= 0) pstr[t] = pstr[s] * p_sym[a];
                 }
             }
         });
     }
-    // output-free states as (log-probability, breadth-first position); the
-    // most likely come first, ties in breadth-first order (the root, with
-    // log-probability 0, is first)
+    std::vector<double> visit(pstr);
+    for (uint32_t s = 1; s < S; ++s) visit[fail[s]] -= pstr[s];
+    visit[0] = 2.0;  // the root is state 0: every chain starts there
     struct Rank {
         double lp;
         uint32_t pos;
@@ -315,7 +327,7 @@ int compile_automaton(const uint8_t *symbols, const uint64_t *offsets, uint32_t 
     std::vector<Rank> free_states;
     free_states.reserve(S);
     for (uint32_t k = 0; k < S; ++k)
-        if (set_len[bfs[k]] == 0) free_states.push_back(Rank{logp[bfs[k]], k});
+        if (set_len[bfs[k]] == 0) free_states.push_back(Rank{visit[bfs[k]], k});
     const auto before = [](const Rank &x, const Rank &y) {
         return x.lp > y.lp || (x.lp == y.lp && x.pos < y.pos);
     };

@@ -91,6 +91,8 @@ struct Inst {
     const uint32_t *delta2;  // two-symbol transitions (stride2 only)
     uint32_t stride2;        // 1: the count pass walks two symbols per lookup from LDS
     uint32_t fo2_bytes;      // first output row offset in the two-symbol table
+    uint32_t walk_sz;        // 1: the emit walks read the count table (masked), which the
+                             // count pass has just pulled into L2, instead of delta
 };
 
 struct TileDesc {
@@ -297,22 +299,39 @@ __device__ __forceinline__ void walk_count(const UTable<PLACE, ROW16> &tab, cons
 // (byte hot / 2).  The next entry is then (h << 4) | v for every lane.
 constexpr uint32_t kRowBits = 0x00FFFFFFu;  // row offset part of a count-table entry
 
+// The table the emit kernels walk: the count table, masked to row offsets,
+// when the count pass walked it (it is then in L2, while delta is not),
+// else delta.
+struct MTable {
+    rsrc_t g;
+    uint32_t mask;
+    __device__ __forceinline__ uint32_t operator()(uint32_t a) const { return buf_load(g, a) & mask; }
+};
+__device__ __forceinline__ MTable emit_table(const uint32_t *delta, const uint32_t *delta_sz,
+                                             uint32_t walk_sz, uint32_t bytes) {
+    return walk_sz ? MTable{make_rsrc(delta_sz, bytes), kRowBits}
+                   : MTable{make_rsrc(delta, bytes), 0xFFFFFFFFu};
+}
+
 struct HotTable16 {
     rsrc_t g;      // count table
+    rsrc_t gc;     // the same from the first row not in LDS on
     uint32_t hot;  // first row offset not in LDS
     // One lookup for each of CH independent chains: every chain's global
     // and LDS reads are issued before any result is used, and the rare
     // escape is tested once for all chains, so the chains' latencies
-    // overlap inside the wave.
+    // overlap inside the wave.  The cold rows are addressed from `hot` on:
+    // a lane on a row in LDS gives an offset that wraps past the end of
+    // that range, so its load returns 0 with no memory access and the
+    // step needs no select.
     template <int CH>
     __device__ __forceinline__ void step(const uint32_t (&a)[CH], uint32_t (&r)[CH]) const {
-        constexpr uint32_t kNoRead = 0xFFFFFFF0u;
         // the 16-bit rows start at LDS address 0 (the count kernel has no
         // static LDS; the host checks that before choosing this walk)
         typedef __attribute__((address_space(3))) uint16_t lds_u16;
         uint32_t v[CH], h[CH];
 #pragma unroll
-        for (int c = 0; c < CH; ++c) v[c] = buf_load(g, a[c] < hot ? kNoRead : a[c]);
+        for (int c = 0; c < CH; ++c) v[c] = buf_load(gc, a[c] - hot);
 #pragma unroll
         for (int c = 0; c < CH; ++c) h[c] = *(const lds_u16 *)(uintptr_t)(min(a[c], hot) >> 1);
         bool esc = false;
@@ -754,7 +773,10 @@ __global__ __launch_bounds__(kMaxCountThreads) void k_count(
             done = true;
         } else if constexpr (MODE == kCountHybrid) {
             if constexpr (FMT == AC_TEXT_2BIT)
-                walk_count_h16<CH>(HotTable16{make_rsrc(uniform(I.delta_sz), table_bytes), hot},
+                walk_count_h16<CH>(HotTable16{make_rsrc(uniform(I.delta_sz), table_bytes),
+                                           make_rsrc((const uint8_t *)uniform(I.delta_sz) + hot,
+                                                     table_bytes - hot),
+                                           hot},
                                    txt, fo, chunk, warm, in, seg_state, seg_m, co);
             else
                 walk_count<FMT, PL_HYBRID, CH>(UTable<PL_HYBRID>{gtab, hot, row}, txt, out_size,
@@ -1044,7 +1066,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
             } else if constexpr (BATCH) {
                 walk(LTable{I.delta, I.table_bytes}, LText{(const uint32_t *)I.text, I.text_bytes4});
             } else {
-                walk(UTable<PL_GLOBAL>{make_rsrc(single.delta, single.table_bytes), 0, 0},
+                walk(emit_table(single.delta, single.delta_sz, single.walk_sz, single.table_bytes),
                      UText{make_rsrc(single.text, single.text_bytes4), single.text_bytes4});
             }
             for (uint32_t j = 0; j < ne; ++j) {
@@ -1210,7 +1232,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_emit_dense(
     for (uint32_t w = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * B; w < n_dense;
          w += waves * B) {
         uint32_t idx[B], seg[B], s[B], mine[B];
-        UTable<PL_GLOBAL> tab[B];
+        MTable tab[B];
         UText txt[B];
 #pragma unroll
         for (uint32_t b = 0; b < B; ++b) {
@@ -1224,7 +1246,8 @@ __global__ __launch_bounds__(kDenseThreads) void k_emit_dense(
                                                                     : uniform(qs.w);
             mine[b] = 0;
             const uint32_t tb4 = uniform(I.text_bytes4);
-            tab[b] = UTable<PL_GLOBAL>{make_rsrc(uniform(I.delta), uniform(I.table_bytes)), 0, 0};
+            tab[b] = emit_table(uniform(I.delta), uniform(I.delta_sz), uniform(I.walk_sz),
+                                uniform(I.table_bytes));
             txt[b] = UText{make_rsrc(uniform(I.text), tb4), tb4};
         }
 #pragma unroll
@@ -1374,7 +1397,8 @@ __global__ __launch_bounds__(kDenseLdsThreads) void k_emit_dense_lds(
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t gq = lane / kQuarter;
     const uint32_t waves = gridDim.x * (blockDim.x >> 6);
-    const UTable<PL_GLOBAL> tab{make_rsrc(uniform(I.delta), uniform(I.table_bytes)), 0, 0};
+    const MTable tab = emit_table(uniform(I.delta), uniform(I.delta_sz), uniform(I.walk_sz),
+                                  uniform(I.table_bytes));
     const uint32_t tb4 = uniform(I.text_bytes4);
     const UText txt{make_rsrc(uniform(I.text), tb4), tb4};
     const uint32_t fo = uniform(I.fo_bytes), fos = uniform(I.fo_state);
@@ -2146,6 +2170,9 @@ static int launch_single(const Geom &g, const Inst &I, const Workspace &w, hipSt
                                             : kCountAny;
     int rc = launch_count<FMT, false>(g, I, nullptr, nullptr, w, mode, 0, T, st);
     if (rc) return rc;
+    // the emit walks follow the table the count pass read
+    Inst E = I;
+    E.walk_sz = mode == kCountHybrid && FMT == AC_TEXT_2BIT && I.delta_sz ? 1u : 0u;
     {
         KTimer tm(AC_K_OFFSETS, st);
         hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, w.tile_m, w.tile_zs,
@@ -2163,7 +2190,7 @@ static int launch_single(const Geom &g, const Inst &I, const Workspace &w, hipSt
         KTimer tm(AC_K_EMIT, st);
         hipLaunchKernelGGL((k_emit<FMT, false>),
                            dim3(resident_grid(k_emit<FMT, false>, kEmitThreads, g.grid_emit)),
-                           dim3(kEmitThreads), 0, st, I,
+                           dim3(kEmitThreads), 0, st, E,
                            nullptr, w.list_seg, w.list_state, w.list_moff, nullptr, w.totals,
                            w.seg_state, g.chunk / kSeg);
     }
@@ -2181,7 +2208,7 @@ static int launch_single(const Geom &g, const Inst &I, const Workspace &w, hipSt
         hipLaunchKernelGGL((k_emit_dense_lds<FMT>),
                            dim3(resident_grid(k_emit_dense_lds<FMT>, kDenseLdsThreads,
                                               g.grid_dense, dyn)),
-                           dim3(kDenseLdsThreads), dyn, st, I, w.list_seg, w.list_state,
+                           dim3(kDenseLdsThreads), dyn, st, E, w.list_seg, w.list_state,
                            w.list_moff, w.totals, (uint32_t)off_bytes, (uint32_t)ids_bytes,
                            I.out);
     } else {
@@ -2190,7 +2217,7 @@ static int launch_single(const Geom &g, const Inst &I, const Workspace &w, hipSt
                            dim3(resident_grid(k_emit_dense<FMT, false>, kDenseThreads,
                                               g.grid_dense)),
                            dim3(kDenseThreads), 0,
-                           st, I, nullptr, w.list_seg, w.list_state, w.list_moff, nullptr,
+                           st, E, nullptr, w.list_seg, w.list_state, w.list_moff, nullptr,
                            w.totals, I.out_ids, I.out);
     }
     HIP_OK(hipGetLastError());
