@@ -72,6 +72,12 @@ extern "C" {
                              * symbols at once (states x 16 entries) in LDS,
                              * one lookup per two bases; needs states * 64
                              * bytes of LDS, else falls back to AC_PLACE_LDS */
+#define AC_PLACE_LDS16 5    /* whole table in LDS as 16-bit state ids (sigma *
+                             * 2 bytes per row; dictionaries of fewer than
+                             * 65,535 states): the default when the 32-bit
+                             * table does not fit LDS but this one does; a
+                             * request that does not fit falls back to
+                             * AC_PLACE_HYBRID */
 
 #define AC_BUILD_HOST_ONLY 1u /* compile tables on the host only (no GPU)   */
 #define AC_BUILD_SERIAL 2u    /* compile on one host thread (default: up to 16

@@ -40,7 +40,8 @@ AC_TEXT_U8 = 0
 AC_TEXT_2BIT = 1
 AC_ALPHA_DNA = 0
 AC_ALPHA_PROTEIN = 1
-AC_PLACE_AUTO, AC_PLACE_LDS, AC_PLACE_GLOBAL, AC_PLACE_HYBRID, AC_PLACE_LDS2 = 0, 1, 2, 3, 4
+AC_PLACE_AUTO, AC_PLACE_LDS, AC_PLACE_GLOBAL, AC_PLACE_HYBRID, AC_PLACE_LDS2, AC_PLACE_LDS16 = \
+    0, 1, 2, 3, 4, 5
 AC_BUILD_HOST_ONLY = 1
 AC_BUILD_SERIAL = 2
 AC_SEGMENT = 64

@@ -32,7 +32,7 @@ int ac_build(const uint8_t *symbols, const uint64_t *offsets, uint32_t n_pattern
     *out = nullptr;
     ac_build_opts o = {4, AC_PLACE_AUTO, 0, 0};
     if (opts) o = *opts;
-    if (o.placement > AC_PLACE_LDS2 || (o.flags & ~(AC_BUILD_HOST_ONLY | AC_BUILD_SERIAL)))
+    if (o.placement > AC_PLACE_LDS16 || (o.flags & ~(AC_BUILD_HOST_ONLY | AC_BUILD_SERIAL)))
         return AC_E_INVALID;
     ac_dict *d = acx::test_alloc_fails() ? nullptr : new (std::nothrow) ac_dict();
     if (!d) return AC_E_NOMEM;
@@ -78,7 +78,7 @@ int ac_build_partitioned(const uint8_t *symbols, const uint64_t *offsets, uint32
     if (!offsets || n_patterns == 0 || offsets[0] != 0) return AC_E_INVALID;
     ac_build_opts o = {4, AC_PLACE_AUTO, 0, 0};
     if (opts) o = *opts;
-    if (o.sigma < 2 || o.sigma > 256 || o.placement > AC_PLACE_LDS2 ||
+    if (o.sigma < 2 || o.sigma > 256 || o.placement > AC_PLACE_LDS16 ||
         (o.flags & ~(AC_BUILD_HOST_ONLY | AC_BUILD_SERIAL)))
         return AC_E_INVALID;
     if (parts > n_patterns) parts = n_patterns;

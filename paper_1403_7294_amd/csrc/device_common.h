@@ -15,7 +15,7 @@ typedef __amdgpu_buffer_rsrc_t rsrc_t;
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
 typedef __attribute__((address_space(3))) uint8_t lds_u8;
 
-enum { PL_LDS = 1, PL_GLOBAL = 2, PL_HYBRID = 3 };
+enum { PL_LDS = 1, PL_GLOBAL = 2, PL_HYBRID = 3, PL_LDS16 = 4 };
 
 // A raw buffer resource over [p, p + bytes): loads at offsets >= bytes
 // return 0 instead of touching memory (gfx9 buffer range checking).
@@ -150,6 +150,8 @@ __device__ __forceinline__ uint32_t lds_load_u16(uint32_t byte_addr) {
 // a = row offset + 4 * symbol in the 32-bit table and return the next
 // state's row offset.
 //   PL_LDS     the whole 32-bit table is in LDS;
+//   PL_LDS16   the whole table is in LDS as 16-bit state ids, at half the
+//              byte address;
 //   PL_GLOBAL  the table is read through the L1/L2 caches;
 //   PL_HYBRID  rows below `hot` (a byte bound in the 32-bit table) are in
 //              LDS as 16-bit state ids, at half the byte address; an id of
@@ -163,6 +165,9 @@ struct UTable {
     __device__ __forceinline__ uint32_t operator()(uint32_t a) const {
         if constexpr (PLACE == PL_LDS) {
             return lds_load(a);
+        } else if constexpr (PLACE == PL_LDS16) {
+            const uint32_t h = lds_load_u16(a >> 1);
+            return ROW16 ? h << 4 : h * row;
         } else if constexpr (PLACE == PL_GLOBAL) {
             return buf_load(g, a);
         } else {

@@ -79,6 +79,10 @@ struct ac_dict {
     uint16_t *d_hot16 = nullptr;  // first hot16_rows rows as 16-bit ids (0xFFFF: see table)
     uint16_t *d_hot16c = nullptr;  // the same, output targets also 0xFFFF (count-table walk)
     uint32_t hot16_rows = 0;
+    // the whole table as 16-bit state ids (states < 65,535 and the table
+    // fits LDS), for AC_PLACE_LDS16
+    uint16_t *d_tab16 = nullptr;
+    uint32_t tab16_bytes = 0;
     // sigma 4 only, when it fits LDS: transitions over two symbols,
     // states x 16 entries; entry = next row offset (next * 64), bit 31 set
     // when the state after the first symbol has an output set

@@ -70,6 +70,7 @@ struct Inst {
     uint32_t n_ids;            // entries of out_ids
     const uint16_t *hot16;   // 16-bit rows for the hybrid placement
     const uint16_t *hot16c;  // the same with every output target escaped (count-table walk)
+    const uint16_t *tab16;   // the whole table as 16-bit ids (lds_all == 2)
     const uint8_t *text;
     ac_match *out;
     unsigned long long *count;
@@ -80,7 +81,7 @@ struct Inst {
     uint32_t fo_bytes;     // row offset of the first state with output
     uint32_t fo_state;     // its state number
     uint32_t hot_bytes;    // LDS: table bytes; hybrid: first row offset not in LDS; else 0
-    uint32_t lds_all;      // 1: whole table in LDS (with zero pad)
+    uint32_t lds_all;      // 1: whole table in LDS (with zero pad); 2: as 16-bit ids
     uint32_t lds_bytes;    // bytes the count kernel copies into LDS
     uint32_t n_chunks;
     uint32_t chunk_base;   // first chunk of this instance in the chunk arrays
@@ -228,7 +229,7 @@ __device__ __forceinline__ void walk_count(const UTable<PLACE, ROW16> &tab, cons
                             ne[c] = kEvSlots + 1;
                             continue;
                         }
-                        if constexpr (PLACE == PL_LDS) {
+                        if constexpr (PLACE == PL_LDS || PLACE == PL_LDS16) {
                             // small tables: one position at a time (fewer
                             // registers; the lookups are cheap)
 #pragma unroll
@@ -734,6 +735,8 @@ __global__ __launch_bounds__(kMaxCountThreads) void k_count(
                 __syncthreads();
                 if (uniform(I.stride2))
                     load_lds_table(make_rsrc(uniform(I.delta2), lb), lb);
+                else if (lds_all == 2)
+                    load_lds_table(make_rsrc(uniform(I.tab16), table_bytes >> 1), lb);
                 else if (lds_all)
                     load_lds_table(gtab, lb);
                 else  // 16-bit rows, then zeros up to lb
@@ -768,8 +771,14 @@ __global__ __launch_bounds__(kMaxCountThreads) void k_count(
         ChunkOut co[CH];
         bool done = false;
         if constexpr (MODE == kCountLds) {
-            walk_count<FMT, PL_LDS, CH>(UTable<PL_LDS>{gtab, hot, row}, txt, out_size, size_bytes,
-                                        fo, fos, tz, inv, chunk, warm, in, seg_state, seg_m, co);
+            if (lds_all == 2)
+                walk_count<FMT, PL_LDS16, CH, FMT == AC_TEXT_2BIT>(
+                    UTable<PL_LDS16, FMT == AC_TEXT_2BIT>{gtab, hot, row}, txt, out_size,
+                    size_bytes, fo, fos, tz, inv, chunk, warm, in, seg_state, seg_m, co);
+            else
+                walk_count<FMT, PL_LDS, CH>(UTable<PL_LDS>{gtab, hot, row}, txt, out_size,
+                                            size_bytes, fo, fos, tz, inv, chunk, warm, in,
+                                            seg_state, seg_m, co);
             done = true;
         } else if constexpr (MODE == kCountHybrid) {
             if constexpr (FMT == AC_TEXT_2BIT)
@@ -791,6 +800,10 @@ __global__ __launch_bounds__(kMaxCountThreads) void k_count(
             }
         }
         if (done) {
+        } else if (lds_all == 2) {
+            walk_count<FMT, PL_LDS16, CH, FMT == AC_TEXT_2BIT>(
+                UTable<PL_LDS16, FMT == AC_TEXT_2BIT>{gtab, hot, row}, txt, out_size, size_bytes,
+                fo, fos, tz, inv, chunk, warm, in, seg_state, seg_m, co);
         } else if (lds_all) {
             walk_count<FMT, PL_LDS, CH>(UTable<PL_LDS>{gtab, hot, row}, txt, out_size, size_bytes,
                                         fo, fos, tz, inv, chunk, warm, in, seg_state, seg_m, co);
@@ -1699,6 +1712,14 @@ int upload_dict(ac_dict *d) {
     for (size_t i = 0; i < (size_t)hot_rows * T.sigma; ++i)
         if (T.delta[i] >= T.first_output) hot16c[i] = 0xFFFFu;
     d->hot16_rows = hot_rows;
+    // every row as 16-bit ids, when all ids fit 16 bits and the table fits
+    // the count kernel's LDS beside its zero pad
+    std::vector<uint16_t> tab16;
+    const uint64_t t16 = (uint64_t)T.states * T.sigma * 2u;
+    if (T.states < 0xFFFFu && t16 + kLdsPad / 2 <= count_lds_limit(lds)) {
+        tab16.resize(T.delta.size() + 2, 0);  // (+2: the LDS copy reads whole words)
+        for (size_t i = 0; i < T.delta.size(); ++i) tab16[i] = (uint16_t)T.delta[i];
+    }
     // two-symbol table, when it fits the count kernel's LDS
     std::vector<uint32_t> d2;
     if (T.sigma == 4 && (uint64_t)T.states * 64u <= count_lds_limit(lds)) {
@@ -1746,6 +1767,7 @@ int upload_dict(ac_dict *d) {
         hipMalloc((void **)&d->d_hot16, hot16.size() * 2) != hipSuccess ||
         hipMalloc((void **)&d->d_hot16c, hot16c.size() * 2) != hipSuccess ||
         (!dsz.empty() && hipMalloc((void **)&d->d_delta_sz, dsz.size() * 4) != hipSuccess) ||
+        (!tab16.empty() && hipMalloc((void **)&d->d_tab16, tab16.size() * 2) != hipSuccess) ||
         (!d2.empty() && hipMalloc((void **)&d->d_delta2, d2.size() * 4) != hipSuccess) ||
         (!go.empty() && (hipMalloc((void **)&d->d_go, go.size() * 4) != hipSuccess ||
                          hipMalloc((void **)&d->d_own_off, T.own_off.size() * 4) != hipSuccess ||
@@ -1770,6 +1792,8 @@ int upload_dict(ac_dict *d) {
              hipSuccess) ||
         (!d2.empty() &&
          hipMemcpy(d->d_delta2, d2.data(), d2.size() * 4, hipMemcpyHostToDevice) != hipSuccess) ||
+        (!tab16.empty() && hipMemcpy(d->d_tab16, tab16.data(), tab16.size() * 2,
+                                     hipMemcpyHostToDevice) != hipSuccess) ||
         (!go.empty() &&
          (hipMemcpy(d->d_go, go.data(), go.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
           hipMemcpy(d->d_own_off, T.own_off.data(), T.own_off.size() * 4,
@@ -1781,6 +1805,7 @@ int upload_dict(ac_dict *d) {
         return AC_E_HIP;
     }
     d->delta2_bytes = (uint32_t)(d2.size() * 4);
+    d->tab16_bytes = tab16.empty() ? 0u : (uint32_t)t16;
     d->device = dev;
     return AC_OK;
 }
@@ -1794,6 +1819,9 @@ void release_dict(ac_dict *d) {
     if (d->d_hot16) (void)hipFree(d->d_hot16);
     if (d->d_hot16c) (void)hipFree(d->d_hot16c);
     d->d_hot16c = nullptr;
+    if (d->d_tab16) (void)hipFree(d->d_tab16);
+    d->d_tab16 = nullptr;
+    d->tab16_bytes = 0;
     if (d->d_delta_sz) (void)hipFree(d->d_delta_sz);
     d->d_delta_sz = nullptr;
     if (d->d_delta2) (void)hipFree(d->d_delta2);
@@ -1939,8 +1967,17 @@ static Placement choose_placement(const ac_dict *d, uint32_t requested, uint32_t
         }
         p = AC_PLACE_LDS;
     }
-    if (p == AC_PLACE_AUTO) p = fits ? AC_PLACE_LDS : AC_PLACE_HYBRID;
+    const bool fits16 = d->d_tab16 && d->tab16_bytes + kLdsPad / 2 <= lds_limit;
+    if (p == AC_PLACE_AUTO) p = fits ? AC_PLACE_LDS : fits16 ? AC_PLACE_LDS16 : AC_PLACE_HYBRID;
     if (p == AC_PLACE_LDS && !fits) p = AC_PLACE_HYBRID;
+    if (p == AC_PLACE_LDS16 && !fits16) p = AC_PLACE_HYBRID;
+    if (p == AC_PLACE_LDS16) {
+        // 16-bit ids of every row, then zeros
+        pl.hot = tb;
+        pl.lds_all = 2;
+        pl.lds_bytes = ((d->tab16_bytes + 3u) & ~3u) + kLdsPad / 2;
+        return pl;
+    }
     if (p == AC_PLACE_HYBRID && d->hot16_rows == 0) p = AC_PLACE_GLOBAL;
     if (p == AC_PLACE_LDS) {
         pl.hot = tb;
@@ -1997,7 +2034,7 @@ static int resolve_geom(const ac_dict *const *dicts, const uint64_t *ns, uint32_
     // LDS need of the count kernel
     uint32_t lds_bytes = 0;
     const uint32_t req = tune ? tune->placement : 0;
-    if (req > AC_PLACE_LDS2) return AC_E_INVALID;
+    if (req > AC_PLACE_LDS16) return AC_E_INVALID;
     for (uint32_t i = 0; i < n_inst; ++i)
         lds_bytes = std::max(lds_bytes, choose_placement(dicts[i], req, lds_limit, fmt).lds_bytes);
     g->lds_bytes = lds_bytes;
@@ -2059,6 +2096,7 @@ static void fill_inst(const ac_dict *d, const void *text, uint64_t n, uint32_t f
     I->lds_bytes = pl.lds_bytes;
     I->hot16 = d->d_hot16;
     I->hot16c = d->d_hot16c;
+    I->tab16 = d->d_tab16;
     const RowDiv rd = make_row_div(d->host.sigma);
     I->div_tz = rd.tz;
     I->div_inv = rd.inv;

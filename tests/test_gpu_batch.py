@@ -95,3 +95,29 @@ def test_batch_plan_replay_and_graph():
         torch.cuda.synchronize()
         _check(wants, outs, counts)
     plan.close()
+
+
+def test_batch_with_lds16_instances():
+    # instances whose 32-bit table exceeds LDS while the 16-bit one fits are
+    # counted with the whole-table LDS instances
+    torch = torch_cuda()
+    rng = W.rng_for(77)
+    insts = W.batch(scale=1 / 64, count=10)
+    for k in range(4):
+        n = int(rng.integers(20_000, 200_000))
+        text = rng.integers(0, 4, size=n, dtype=np.uint8)
+        text[n // 3:n // 3 + 300] = 0
+        pats = [np.zeros(10, np.uint8)]
+        pats += W._cut(rng, text, rng.integers(8, 21, size=500))
+        pats += [rng.integers(0, 4, size=int(L), dtype=np.uint8)
+                 for L in rng.integers(8, 21, size=600 + 50 * k)]
+        insts.insert(3 * k, W.Instance(text, W.PatternSet.from_list(pats), 4, W.DNA, "lds16"))
+    dicts, wants, outs, counts, items = _setup(insts, ac.AC_TEXT_2BIT)
+    _, lds = ac.ac_device_info()
+    assert sum(1 for d in dicts if d.info.states * 16 + 1024 > lds - 512
+               and d.info.states * 8 + 512 <= lds - 512) >= 3
+    for tune in (None, {"chunk": 64, "block_threads": 512}, {"chains": 2}):
+        counts.fill_(-1)
+        ac.ac_scan_batch(items, tune=tune)
+        torch.cuda.synchronize()
+        _check(wants, outs, counts)

@@ -360,3 +360,49 @@ def test_output_buffer_not_16_byte_aligned():
     assert int(cnt.item()) == len(want)
     assert np.array_equal(ac.match_keys(out[:len(want)]), want)
     assert (buf[0] == -1).all() and (buf[len(want) + 1:] == -1).all()
+
+
+# ------------------------------------------------------------ 16-bit whole table in LDS
+
+def _lds16_instance(seed=61, n=600_000):
+    # about 13 K states: the 32-bit table (16 B a row) exceeds LDS, the
+    # 16-bit one (8 B a row) fits; poly-A runs and A^k patterns give dense
+    # segments, cut patterns give sparse ones
+    rng = W.rng_for(seed)
+    text = rng.integers(0, 4, size=n, dtype=np.uint8)
+    for start in range(5000, n - 1000, 40_000):
+        text[start:start + int(rng.integers(50, 500))] = 0
+    pats = [np.zeros(k, np.uint8) for k in range(8, 17)]
+    pats += W._cut(rng, text, rng.integers(8, 21, size=560))
+    pats += [rng.integers(0, 4, size=int(L), dtype=np.uint8) for L in rng.integers(8, 21, size=560)]
+    return W.Instance(text, W.PatternSet.from_list(pats), 4, W.DNA, "lds16")
+
+
+def _lds16_fits(d):
+    _, lds = ac.ac_device_info()
+    limit = lds - 512
+    return d.info.states * 16 + 1024 > limit and d.info.states * 8 + 512 <= limit
+
+
+@pytest.mark.parametrize("fmt", [ac.AC_TEXT_2BIT, ac.AC_TEXT_U8])
+@pytest.mark.parametrize("chunk,threads,chains", [(None, None, None), (64, 256, 1),
+                                                  (256, 1024, 2), (1024, 512, 4)])
+def test_lds16_whole_table(fmt, chunk, threads, chains):
+    inst = _lds16_instance()
+    d = ac.ac_build(inst.patterns, sigma=4)
+    assert _lds16_fits(d), d.info.states
+    _say("lds16 states", d.info.states, "fmt", fmt, "chunk", chunk, "threads", threads,
+         "chains", chains)
+    tune = None if chunk is None else {"chunk": chunk, "block_threads": threads, "chains": chains}
+    _parity(inst, fmt, tune=tune, d=d)
+    _parity(inst, fmt, tune=dict(tune or {}, placement=ac.AC_PLACE_LDS16), d=d)
+
+
+def test_lds16_requested_on_small_and_large_tables():
+    # a small table may be asked for 16-bit rows; a table too large for them
+    # falls back to the hybrid placement
+    small = W.dna_small(scale=1 / 4)
+    _parity(small, ac.AC_TEXT_2BIT, tune={"placement": ac.AC_PLACE_LDS16})
+    _parity(small, ac.AC_TEXT_U8, tune={"placement": ac.AC_PLACE_LDS16, "chunk": 128})
+    big = W.dna_dense(scale=1 / 1024)
+    _parity(big, ac.AC_TEXT_2BIT, tune={"placement": ac.AC_PLACE_LDS16})
