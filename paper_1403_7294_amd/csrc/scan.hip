@@ -85,6 +85,9 @@ struct Inst {
     uint32_t lds_bytes;    // bytes the count kernel copies into LDS
     uint32_t n_chunks;
     uint32_t chunk_base;   // first chunk of this instance in the chunk arrays
+    uint32_t seg_base;     // its first segment in the segment arrays
+    uint32_t chunk;        // symbols per chunk (a multiple of the segment)
+    uint32_t warm;         // text words walked before a chunk (max_len - 1 symbols, rounded up)
     uint32_t first_tile;   // first tile of this instance
     uint32_t n_tiles;
     uint32_t div_tz, div_inv;
@@ -695,7 +698,7 @@ constexpr int kCountAny = 0, kCountLds = 1, kCountHybrid = 2;
 template <int FMT, bool BATCH, int CH, int MODE = kCountAny>
 __global__ __launch_bounds__(kMaxCountThreads) void k_count(
     Inst single, const Inst *__restrict__ insts, const TileDesc *__restrict__ tiles,
-    uint32_t t_base, uint32_t n_tiles, uint32_t chunk, uint32_t warm, uint32_t red_off,
+    uint32_t t_base, uint32_t n_tiles, uint32_t red_off,
     uint32_t *__restrict__ cnt,
     uint32_t *__restrict__ mask, u32x4 *__restrict__ seg_state, uint32_t *__restrict__ seg_m,
     unsigned long long *__restrict__ tile_m, uint32_t *__restrict__ tile_zs,
@@ -707,7 +710,6 @@ __global__ __launch_bounds__(kMaxCountThreads) void k_count(
     lds_u64 *red_a = (lds_u64 *)((lds_u8 *)(lds_u32 *)dyn_smem + red_off);
     lds_u32 *red_b = (lds_u32 *)((lds_u8 *)(lds_u32 *)dyn_smem + red_off + 128u);
     lds_u32 *red_c = red_b + 16;
-    const uint32_t spc = chunk / kSeg;
     // this launch covers tiles t_base .. t_base + n_tiles - 1
     const uint32_t t0 = t_base + (uint32_t)(((uint64_t)n_tiles * blockIdx.x) / gridDim.x);
     const uint32_t t1 = t_base + (uint32_t)(((uint64_t)n_tiles * (blockIdx.x + 1)) / gridDim.x);
@@ -758,6 +760,8 @@ __global__ __launch_bounds__(kMaxCountThreads) void k_count(
         const uint32_t size_bytes = (uniform(I.table_bytes) / row - fos) * 4u;
         const uint32_t tz = uniform(I.div_tz), inv = uniform(I.div_inv);
         const uint32_t cbase = uniform(I.chunk_base);
+        const uint32_t chunk = uniform(I.chunk), warm = uniform(I.warm);
+        const uint32_t spc = chunk / kSeg, sbase = uniform(I.seg_base);
         ChainIn in[CH];
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
@@ -766,7 +770,7 @@ __global__ __launch_bounds__(kMaxCountThreads) void k_count(
             in[c].j = valid ? first + k : first;
             const uint64_t begin = (uint64_t)in[c].j * chunk;
             in[c].lim = valid ? (uint32_t)min<uint64_t>(chunk, n - begin) : 0u;
-            in[c].seg0 = (cbase + in[c].j) * spc;
+            in[c].seg0 = sbase + in[c].j * spc;
         }
         ChunkOut co[CH];
         bool done = false;
@@ -903,7 +907,7 @@ __global__ __launch_bounds__(1024) void k_tile_scan(
 template <bool BATCH>
 __global__ __launch_bounds__(kMaxCountThreads) void k_scatter(
     Inst single, const Inst *__restrict__ insts, const TileDesc *__restrict__ tiles,
-    uint32_t chunk, uint32_t per, const uint32_t *__restrict__ cnt,
+    uint32_t per, const uint32_t *__restrict__ cnt,
     const uint32_t *__restrict__ mask, const u32x4 *__restrict__ seg_state,
     const uint32_t *__restrict__ seg_m, const unsigned long long *__restrict__ tile_moff,
     const uint32_t *__restrict__ tile_zsoff, const uint32_t *__restrict__ tile_zdoff,
@@ -911,7 +915,6 @@ __global__ __launch_bounds__(kMaxCountThreads) void k_scatter(
     u32x4 *__restrict__ list_state, unsigned long long *__restrict__ list_moff,
     uint32_t *__restrict__ list_inst) {
     const uint32_t t = blockIdx.x;
-    const uint32_t spc = chunk / kSeg;
     uint32_t inst = 0, first, count, cbase = 0;
     unsigned long long base_off = 0;
     if constexpr (BATCH) {
@@ -925,6 +928,8 @@ __global__ __launch_bounds__(kMaxCountThreads) void k_scatter(
         first = t * blockDim.x * per;
         count = min(blockDim.x * per, single.n_chunks - first);
     }
+    const Inst &I = BATCH ? insts[inst] : single;
+    const uint32_t spc = I.chunk / kSeg, sbase = I.seg_base;
     const uint32_t k0 = threadIdx.x * per;
     const uint32_t k1 = min(k0 + per, count);
     unsigned long long m = 0;
@@ -934,7 +939,8 @@ __global__ __launch_bounds__(kMaxCountThreads) void k_scatter(
         m += cnt[g];
         const uint32_t mk = mask[g];
         uint32_t d = 0;
-        for (uint32_t b = mk; b; b &= b - 1) d += seg_m[g * spc + __builtin_ctz(b)] >= kDenseMatches;
+        const uint32_t s0 = sbase + (first + k) * spc;
+        for (uint32_t b = mk; b; b &= b - 1) d += seg_m[s0 + __builtin_ctz(b)] >= kDenseMatches;
         zd += d;
         zs += __builtin_popcount(mk) - d;
     }
@@ -949,7 +955,7 @@ __global__ __launch_bounds__(kMaxCountThreads) void k_scatter(
         const uint32_t g = cbase + j;
         for (uint32_t b = mask[g]; b; b &= b - 1) {
             const uint32_t i = __builtin_ctz(b);
-            const uint32_t gs = g * spc + i;
+            const uint32_t gs = sbase + j * spc + i;
             const uint32_t sm = seg_m[gs];
             const uint32_t kk = sm >= kDenseMatches ? kd++ : ks++;
             list_seg[kk] = j * spc + i;
@@ -1019,7 +1025,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
     Inst single, const Inst *__restrict__ insts, const uint32_t *__restrict__ list_seg,
     const u32x4 *__restrict__ list_state, const unsigned long long *__restrict__ list_moff,
     const uint32_t *__restrict__ list_inst, const unsigned long long *__restrict__ totals,
-    const u32x4 *__restrict__ seg_rec, uint32_t spc) {
+    const u32x4 *__restrict__ seg_rec) {
     constexpr uint32_t SPW = Fmt<FMT>::SPW;
     constexpr uint32_t WPS = kSeg / SPW;
     constexpr uint32_t WPQ = kQuarter / SPW;  // text words per quarter
@@ -1049,8 +1055,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
             const uint32_t lim = min(kSeg, I.n - e0);
             const uint32_t fo = I.fo_bytes, fos = I.fo_state, tz = I.div_tz, inv = I.div_inv;
             const uint32_t *out_off = I.out_off;
-            const uint32_t cb = BATCH ? I.chunk_base : 0u;
-            const u32x4 evs = seg_rec[2 * (cb * spc + seg) + 1];
+            const u32x4 evs = seg_rec[2 * (I.seg_base + seg) + 1];
             auto walk = [&](const auto &tab, const auto &txt) {
                 uint32_t st = q == 0 ? qs.x : q == 1 ? qs.y : q == 2 ? qs.z : qs.w;
 #pragma unroll
@@ -1893,8 +1898,18 @@ struct Geom {
     uint32_t chunk = 0, threads = 0, warm = 0, grid_count = 0, chains = 1;
     uint32_t grid_emit = 0, grid_dense = 0;  // bounded by the largest possible work list
     uint32_t lds_bytes = 0;  // dynamic LDS of k_count
-    uint64_t n_chunks = 0, n_tiles = 0;
-    uint64_t n_segs() const { return n_chunks * (chunk / kSeg); }
+    uint64_t n_chunks = 0, n_tiles = 0, segs = 0;
+    // a batch without a requested chunk size gives an instance too short to
+    // fill one tile shorter chunks, so that more lanes share its text and
+    // its tile's walk ends sooner
+    bool adapt = false;
+    uint64_t n_segs() const { return segs; }
+    uint32_t chunk_of(uint64_t n) const {
+        if (!adapt) return chunk;
+        const uint64_t per_tile = (uint64_t)threads * chains;
+        const uint64_t want = ((n + per_tile - 1) / per_tile + kSeg - 1) / kSeg * kSeg;
+        return (uint32_t)std::max<uint64_t>(kSeg, std::min<uint64_t>(chunk, want));
+    }
 };
 
 struct Workspace {
@@ -2049,12 +2064,16 @@ static int resolve_geom(const ac_dict *const *dicts, const uint64_t *ns, uint32_
         while (chunk > kSeg && (total / chunk) / per_tile < slots) chunk /= 2;
     }
     g->chunk = chunk;
+    g->adapt = n_inst > 1 && !(tune && tune->chunk);
     g->n_chunks = 0;
     g->n_tiles = 0;
+    g->segs = 0;
     for (uint32_t i = 0; i < n_inst; ++i) {
-        const uint64_t c = (ns[i] + chunk - 1) / chunk;
+        const uint32_t ci = g->chunk_of(ns[i]);
+        const uint64_t c = (ns[i] + ci - 1) / ci;
         g->n_chunks += c;
         g->n_tiles += (c + per_tile - 1) / per_tile;
+        g->segs += c * (ci / kSeg);
     }
     if (g->n_chunks >= (1ull << 31) || g->n_tiles >= (1ull << 31)) return AC_E_TOO_LARGE;
     g->grid_count = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g->n_tiles, slots));
@@ -2174,7 +2193,7 @@ static int launch_count_ch(const Geom &g, const Inst &I, const Inst *insts,
     const uint32_t grid = (uint32_t)std::min<uint64_t>(n_tiles, g.grid_count);
     KTimer tm(AC_K_COUNT, st);
     hipLaunchKernelGGL(kc, dim3(grid), dim3(g.threads), dyn, st, I, insts, tiles, t_base,
-                       n_tiles, g.chunk, g.warm, red_off, w.cnt, w.mask, w.seg_state, w.seg_m, w.tile_m,
+                       n_tiles, red_off, w.cnt, w.mask, w.seg_state, w.seg_m, w.tile_m,
                        w.tile_zs, w.tile_zd);
     return AC_OK;
 }
@@ -2220,7 +2239,7 @@ static int launch_single(const Geom &g, const Inst &I, const Workspace &w, hipSt
     {
         KTimer tm(AC_K_SCATTER, st);
         hipLaunchKernelGGL(k_scatter<false>, dim3(T), dim3(g.threads), 0, st, I, nullptr, nullptr,
-                           g.chunk, g.chains, w.cnt, w.mask, w.seg_state, w.seg_m, w.tile_moff,
+                           g.chains, w.cnt, w.mask, w.seg_state, w.seg_m, w.tile_moff,
                            w.tile_zsoff, w.tile_zdoff, w.totals, w.list_seg, w.list_state,
                            w.list_moff, nullptr);
     }
@@ -2230,7 +2249,7 @@ static int launch_single(const Geom &g, const Inst &I, const Workspace &w, hipSt
                            dim3(resident_grid(k_emit<FMT, false>, kEmitThreads, g.grid_emit)),
                            dim3(kEmitThreads), 0, st, E,
                            nullptr, w.list_seg, w.list_state, w.list_moff, nullptr, w.totals,
-                           w.seg_state, g.chunk / kSeg);
+                           w.seg_state);
     }
     // output-set tables for the staged dense emit: offsets (n_out + 1),
     // then ids, both in LDS
@@ -2384,6 +2403,8 @@ int ac_scan(const ac_dict *d, const void *d_text, uint64_t n, uint32_t fmt, ac_m
               count_lds_limit(lds), &I);
     I.n_chunks = (uint32_t)g.n_chunks;
     I.n_tiles = (uint32_t)g.n_tiles;
+    I.chunk = g.chunk;
+    I.warm = g.warm;
     const uint64_t need = ws_layout(g, false, nullptr, nullptr);
     char *ws = (char *)d_workspace;
     bool own = false;
