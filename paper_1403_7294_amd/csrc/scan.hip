@@ -57,7 +57,6 @@ constexpr uint32_t kEvMaxSet = (1u << 26) - 2;
 constexpr uint32_t kMaxChunk = 2048;      // 32 segments: one bit each in a chunk mask
 constexpr uint32_t kDenseMatches = AC_DENSE_SEGMENT_MATCHES;  // listed last, one wave each
 constexpr uint32_t kLdsPad = 1024;        // zero bytes after an LDS table (u8 codes >= sigma)
-constexpr uint32_t kEmitThreads = 256;
 constexpr uint32_t kMaxCountThreads = 1024;
 
 // Per-instance parameters of a scan, shared by host and device.
@@ -1007,106 +1006,161 @@ __device__ __forceinline__ void write_set(ac_match *__restrict__ out, unsigned l
     }
 }
 
-// Sparse part of the work list: four lanes per listed segment.  When the
-// count pass kept the segment's output events (at most four), lane q takes
-// event q and no text is read.  Otherwise lane q walks quarter q (16
-// symbols) from the state the count pass stored for it, so a segment costs
-// 16 dependent lookups instead of 64.  A lane records
-// its output events (state, position) in LDS during the walk -- at most one
-// per position, so 16 slots always suffice -- and writes after the walk:
-// on gfx9 a wave's wait for a load also waits for its earlier stores, so a
-// store inside the lookup chain would stall every later step.  The four
-// lanes of a segment are adjacent in the wave; the offset of each quarter's
-// first match is an exclusive sum of the quarters' match counts over those
-// four lanes.  Within a quarter, events are written in position order and
-// each output set in id order, which is the (end, id) order.
+// One listed sparse segment, four lanes (lane q = quarter q; `act` false on
+// lanes past the list, which still take part in the shuffles).  With up to
+// four kept events lane q writes event q; otherwise lane q walks quarter q
+// (16 symbols) from the state the count pass stored for it, so a segment
+// costs 16 dependent lookups instead of 64.  A walking lane records its
+// output events (state, position) in LDS during the walk -- at most one per
+// position, so 16 slots always suffice -- and writes after the walk: on gfx9
+// a wave's wait for a load also waits for its earlier stores, so a store
+// inside the lookup chain would stall every later step.  The four lanes are
+// adjacent in the wave; the offset of each quarter's first match is an
+// exclusive sum of the quarters' match counts over them.  Within a quarter,
+// events are written in position order and each output set in id order,
+// which is the (end, id) order.
+constexpr uint32_t kEmitThreads = 256;
+
+template <int FMT, bool BATCH>
+__device__ __forceinline__ void emit_group(const Inst &single, const Inst *__restrict__ insts,
+                                           const uint32_t *__restrict__ list_seg,
+                                           const u32x4 *__restrict__ list_state,
+                                           const unsigned long long *__restrict__ list_moff,
+                                           const uint32_t *__restrict__ list_inst,
+                                           const u32x4 *__restrict__ seg_rec, bool act,
+                                           uint32_t idx, uint32_t q, uint32_t tid,
+                                           uint32_t (*ev_set)[kEmitThreads],
+                                           uint8_t (*ev_pos)[kEmitThreads]) {
+    constexpr uint32_t SPW = Fmt<FMT>::SPW;
+    constexpr uint32_t WPS = kSeg / SPW;
+    constexpr uint32_t WPQ = kQuarter / SPW;  // text words per quarter
+    uint32_t ne = 0, matches = 0;
+    uint32_t e0 = 0;
+    unsigned long long off0 = 0;
+    if (act) {
+        const uint32_t inst = BATCH ? list_inst[idx] : 0u;
+        const Inst &I = BATCH ? insts[inst] : single;
+        const uint32_t seg = list_seg[idx];
+        const u32x4 qs = list_state[idx];
+        off0 = list_moff[idx];
+        e0 = seg * kSeg;
+        const uint32_t lim = min(kSeg, I.n - e0);
+        const uint32_t fo = I.fo_bytes, fos = I.fo_state, tz = I.div_tz, inv = I.div_inv;
+        const uint32_t *out_off = I.out_off;
+        const u32x4 evs = seg_rec[2 * (I.seg_base + seg) + 1];
+        auto walk = [&](const auto &tab, const auto &txt) {
+            uint32_t st = q == 0 ? qs.x : q == 1 ? qs.y : q == 2 ? qs.z : qs.w;
+#pragma unroll
+            for (uint32_t w = 0; w < WPQ; ++w) {
+                const uint32_t x = txt.word((int)(seg * WPS + q * WPQ + w));
+#pragma unroll
+                for (uint32_t k = 0; k < SPW; ++k) {
+                    st = tab(st + sym_bytes<FMT>(x, k));
+                    const uint32_t p = q * kQuarter + w * SPW + k;
+                    if (st >= fo && p < lim) {
+                        ev_set[ne][tid] = row_state(st, tz, inv) - fos;
+                        ev_pos[ne][tid] = (uint8_t)p;
+                        ++ne;
+                    }
+                }
+            }
+        };
+        if (evs.x != kEvMany) {
+            // the count pass's events: event q for lane q
+            const uint32_t e = q == 0 ? evs.x : q == 1 ? evs.y : q == 2 ? evs.z : evs.w;
+            if (e != kEvNone) {
+                ev_set[0][tid] = e >> 6;
+                ev_pos[0][tid] = (uint8_t)(e & 63u);
+                ne = 1;
+            }
+        } else if constexpr (BATCH) {
+            walk(LTable{I.delta, I.table_bytes}, LText{(const uint32_t *)I.text, I.text_bytes4});
+        } else {
+            walk(emit_table(single.delta, single.delta_sz, single.walk_sz, single.table_bytes),
+                 UText{make_rsrc(single.text, single.text_bytes4), single.text_bytes4});
+        }
+        for (uint32_t j = 0; j < ne; ++j) {
+            const uint32_t o = ev_set[j][tid];
+            matches += out_off[o + 1] - out_off[o];
+        }
+    }
+    // exclusive sum over the quarters before this one
+    const uint32_t m1 = __shfl_up(matches, 1, 64);
+    const uint32_t m2 = __shfl_up(matches, 2, 64);
+    const uint32_t m3 = __shfl_up(matches, 3, 64);
+    const uint32_t before = (q >= 1 ? m1 : 0u) + (q >= 2 ? m2 : 0u) + (q >= 3 ? m3 : 0u);
+    if (act && ne) {
+        const Inst &I = BATCH ? insts[list_inst[idx]] : single;
+        const uint32_t *out_off = I.out_off;
+        unsigned long long off = off0 + before;
+        for (uint32_t j = 0; j < ne; ++j) {
+            const uint32_t o = ev_set[j][tid];
+            const uint32_t a = out_off[o], len = out_off[o + 1] - a;
+            write_set(I.out, off, I.capacity, I.out_ids, a, len, e0 + ev_pos[j][tid]);
+            off += len;
+        }
+    }
+}
+
+// Sparse part of the work list.  A single scan gives each listed segment one
+// lane first: when the count pass kept a single output event for it (the
+// common case), the lane writes that set itself and no text is read; the
+// wave then takes its other segments four lanes each (emit_group).  A batch
+// (whose count walk keeps up to four events, so that multi-event segments
+// are common) gives every segment four lanes from the start.
 template <int FMT, bool BATCH>
 __global__ __launch_bounds__(kEmitThreads) void k_emit(
     Inst single, const Inst *__restrict__ insts, const uint32_t *__restrict__ list_seg,
     const u32x4 *__restrict__ list_state, const unsigned long long *__restrict__ list_moff,
     const uint32_t *__restrict__ list_inst, const unsigned long long *__restrict__ totals,
     const u32x4 *__restrict__ seg_rec) {
-    constexpr uint32_t SPW = Fmt<FMT>::SPW;
-    constexpr uint32_t WPS = kSeg / SPW;
-    constexpr uint32_t WPQ = kQuarter / SPW;  // text words per quarter
     __shared__ uint32_t ev_set[kQuarter][kEmitThreads];
     __shared__ uint8_t ev_pos[kQuarter][kEmitThreads];
     const uint32_t tid = threadIdx.x;
-    const uint32_t lane = tid & 63;
-    const uint32_t q = tid & 3;
-    const uint32_t items = 4u * (uint32_t)totals[1];
-    // the loop bound is uniform over the wave, so every lane of a segment's
-    // group takes part in the group's shuffles
-    for (uint32_t base = blockIdx.x * blockDim.x + (tid - lane); base < items;
-         base += gridDim.x * blockDim.x) {
-        const uint32_t li = base + lane;
-        const bool act = li < items;
-        const uint32_t idx = act ? li >> 2 : 0u;
-        uint32_t ne = 0, matches = 0;
-        uint32_t e0 = 0;
-        unsigned long long off0 = 0;
-        if (act) {
-            const uint32_t inst = BATCH ? list_inst[idx] : 0u;
-            const Inst &I = BATCH ? insts[inst] : single;
-            const uint32_t seg = list_seg[idx];
-            const u32x4 qs = list_state[idx];
-            off0 = list_moff[idx];
-            e0 = seg * kSeg;
-            const uint32_t lim = min(kSeg, I.n - e0);
-            const uint32_t fo = I.fo_bytes, fos = I.fo_state, tz = I.div_tz, inv = I.div_inv;
-            const uint32_t *out_off = I.out_off;
-            const u32x4 evs = seg_rec[2 * (I.seg_base + seg) + 1];
-            auto walk = [&](const auto &tab, const auto &txt) {
-                uint32_t st = q == 0 ? qs.x : q == 1 ? qs.y : q == 2 ? qs.z : qs.w;
-#pragma unroll
-                for (uint32_t w = 0; w < WPQ; ++w) {
-                    const uint32_t x = txt.word((int)(seg * WPS + q * WPQ + w));
-#pragma unroll
-                    for (uint32_t k = 0; k < SPW; ++k) {
-                        st = tab(st + sym_bytes<FMT>(x, k));
-                        const uint32_t p = q * kQuarter + w * SPW + k;
-                        if (st >= fo && p < lim) {
-                            ev_set[ne][tid] = row_state(st, tz, inv) - fos;
-                            ev_pos[ne][tid] = (uint8_t)p;
-                            ++ne;
-                        }
-                    }
-                }
-            };
-            if (evs.x != kEvMany) {
-                // the count pass's events: event q for lane q
-                const uint32_t e = q == 0 ? evs.x : q == 1 ? evs.y : q == 2 ? evs.z : evs.w;
-                if (e != kEvNone) {
-                    ev_set[0][tid] = e >> 6;
-                    ev_pos[0][tid] = (uint8_t)(e & 63u);
-                    ne = 1;
-                }
-            } else if constexpr (BATCH) {
-                walk(LTable{I.delta, I.table_bytes}, LText{(const uint32_t *)I.text, I.text_bytes4});
-            } else {
-                walk(emit_table(single.delta, single.delta_sz, single.walk_sz, single.table_bytes),
-                     UText{make_rsrc(single.text, single.text_bytes4), single.text_bytes4});
-            }
-            for (uint32_t j = 0; j < ne; ++j) {
-                const uint32_t o = ev_set[j][tid];
-                matches += out_off[o + 1] - out_off[o];
-            }
+    const uint32_t lane = tid & 63, wbase = tid - lane;
+    const uint32_t q = lane & 3;
+    const uint32_t items = (uint32_t)totals[1];
+    // the loop bounds are uniform over the wave, so every lane of a group
+    // takes part in the group's shuffles
+    if constexpr (BATCH) {
+        for (uint32_t base = blockIdx.x * blockDim.x + wbase; base < 4u * items;
+             base += gridDim.x * blockDim.x) {
+            const uint32_t li = base + lane;
+            emit_group<FMT, BATCH>(single, insts, list_seg, list_state, list_moff, list_inst,
+                                   seg_rec, li < 4u * items, li >> 2, q, tid, ev_set, ev_pos);
         }
-        // exclusive sum over the quarters before this one
-        const uint32_t m1 = __shfl_up(matches, 1, 64);
-        const uint32_t m2 = __shfl_up(matches, 2, 64);
-        const uint32_t m3 = __shfl_up(matches, 3, 64);
-        const uint32_t before = (q >= 1 ? m1 : 0u) + (q >= 2 ? m2 : 0u) + (q >= 3 ? m3 : 0u);
-        if (act && ne) {
-            const Inst &I = BATCH ? insts[list_inst[idx]] : single;
-            const uint32_t *out_off = I.out_off;
-            unsigned long long off = off0 + before;
-            for (uint32_t j = 0; j < ne; ++j) {
-                const uint32_t o = ev_set[j][tid];
-                const uint32_t a = out_off[o], len = out_off[o + 1] - a;
-                write_set(I.out, off, I.capacity, I.out_ids, a, len, e0 + ev_pos[j][tid]);
-                off += len;
+    } else {
+        __shared__ uint32_t group_lane[kEmitThreads];  // per wave: lane of its r-th group segment
+        for (uint32_t base = blockIdx.x * blockDim.x + wbase; base < items;
+             base += gridDim.x * blockDim.x) {
+            const uint32_t li = base + lane;
+            bool group = false;
+            if (li < items) {
+                const uint32_t seg = list_seg[li];
+                const u32x4 evs = seg_rec[2 * (single.seg_base + seg) + 1];
+                if (evs.x == kEvMany || evs.y != kEvNone) {
+                    group = true;
+                } else if (evs.x != kEvNone) {
+                    const uint32_t a = single.out_off[evs.x >> 6];
+                    const uint32_t len = single.out_off[(evs.x >> 6) + 1] - a;
+                    write_set(single.out, list_moff[li], single.capacity, single.out_ids, a, len,
+                              seg * kSeg + (evs.x & 63u));
+                }
             }
+            const uint64_t gm = __ballot(group);
+            if (group) group_lane[wbase + __builtin_popcountll(gm & ((1ull << lane) - 1))] = lane;
+            wave_sync();
+            const uint32_t n_group = (uint32_t)__builtin_popcountll(gm);
+            for (uint32_t r0 = 0; r0 < n_group; r0 += 16) {
+                const uint32_t r = r0 + (lane >> 2);
+                const bool act = r < n_group;
+                emit_group<FMT, BATCH>(single, insts, list_seg, list_state, list_moff, list_inst,
+                                       seg_rec, act, act ? base + group_lane[wbase + r] : 0u, q,
+                                       tid, ev_set, ev_pos);
+            }
+            // every lane has read this round's entries before the next round
+            // writes them
+            wave_sync();
         }
     }
 }
