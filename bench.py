@@ -106,7 +106,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=10_000,
                     help="requests timed at the fixed arrival rate")
     ap.add_argument("--scale", type=float, default=1.0, help="shrink the workload (testing)")
-    ap.add_argument("--profile-leg", choices=["protein", "batch", "dna_small"], default=None,
+    ap.add_argument("--profile-leg", choices=["protein", "batch", "dna_small", "serve"],
+                    default=None,
                     help="run only this workload's leg and print its JSON (for kernel traces "
                          "of one workload under rocprofv3); no benchmark line")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -139,7 +140,8 @@ def main():
     if args.profile_leg:
         leg = {"protein": lambda: bench_protein(args, torch, ac, W, dev, stream),
                "batch": lambda: bench_batch(args, torch, ac, W, dev, stream),
-               "dna_small": lambda: bench_small_graph(args, torch, ac, W, dev, stream)}
+               "dna_small": lambda: bench_small_graph(args, torch, ac, W, dev, stream),
+               "serve": lambda: bench_serve(args, torch, ac, W)}
         print(json.dumps({args.profile_leg: leg[args.profile_leg]()}), flush=True)
         return
 
@@ -746,14 +748,18 @@ def bench_serve(args, torch, ac, W):
     fixed arrival rate of 0.7 R_sat."""
     from paper_1403_7294_amd.serve import Server, run_poisson
     t0 = time.time()
-    n_sat = 2000
+    # enough requests that filling and draining the server's pipeline (about
+    # 20 ms) is a small part of the saturated run
+    n_sat = 6000
     wl = W.serve(scale=args.scale, requests=n_sat + args.serve_requests)
     letters = [W.to_ascii(t, W.DNA) for t in wl.texts]
     srv = Server(wl.dictionaries, budget_bytes=8 << 30)
     log(f"[bench] serve: {len(letters)} requests, {sum(len(t) for t in letters)} bases, "
         f"8 dictionaries (setup {time.time() - t0:.1f} s)")
-    # warm-up, then saturation: everything queued at once
-    for f in [srv.submit(letters[k], int(wl.dict_of[k])) for k in range(64)]:
+    # warm-up (a saturated run of its own: the first server of a process
+    # runs its batches markedly slower), then saturation: everything queued
+    # at once
+    for f in [srv.submit(letters[k], int(wl.dict_of[k])) for k in range(2000)]:
         f.result()
     srv.close()
     srv = Server(wl.dictionaries, budget_bytes=8 << 30)
