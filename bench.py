@@ -65,7 +65,7 @@ LDS_LOOKUP_PEAK = 32 * CUS * CLOCK_GHZ * 1e9
 
 
 def scan_roofline(n, matches, ms, text_bytes_per_base, kernel_sum_us, traffic=None):
-    """The scan's place under its roofs (the survey's measurement rule):
+    """The scan's place under its roofs:
     bases/s divided by min(HBM peak / HBM bytes per base, LDS lookup peak /
     one lookup per base).  HBM bytes per base are the algorithmic ones: the
     text read once plus 8 bytes per match written."""
@@ -115,7 +115,7 @@ def main():
                          "scales the FETCH_SIZE / WRITE_SIZE counters to bytes")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build runs on a single MI355X "
+        print("bench.py measures one GPU only: this benchmark runs on a single MI355X "
               "(multi-GPU sharding of the scan is a design note, not built)", file=sys.stderr)
         sys.exit(2)
 

@@ -1,6 +1,6 @@
 // Stand-ins for the GPU half of the library, so that the host half
 // (automaton.cpp, api.cpp) can be built with the host compiler's sanitizers
-// and driven without a GPU.  Dictionaries in this build are host-only: they
+// and driven without a GPU.  Dictionaries in the sanitizer build are host-only: they
 // never reach upload_dict, and release_dict has nothing to free.
 #include "../../paper_1403_7294_amd/csrc/internal.h"
 
